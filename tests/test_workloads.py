@@ -1,0 +1,74 @@
+"""The seeded input generators: code structure and channel statistics."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+@pytest.mark.parametrize("n", [96, 2640, 16384])
+def test_regular_36_codes(n):
+    H = W.gallager36(n)
+    assert H.m == n // 2 and H.nnz == 3 * n
+    assert np.all(H.var_degrees() == 3) and np.all(H.check_degrees() == 6)
+    assert len(H.four_cycle_pairs()) == 0
+    for j in range(0, H.m, max(1, H.m // 50)):
+        row = H.col_idx[H.row_ptr[j]:H.row_ptr[j + 1]]
+        assert np.all(np.diff(row) > 0)
+
+
+def test_regular_48_code():
+    H = W.gallager48(16384)
+    assert H.m == 8192 and H.nnz == 65536
+    assert np.all(H.var_degrees() == 4) and np.all(H.check_degrees() == 8)
+    assert len(H.four_cycle_pairs()) == 0
+
+
+@pytest.mark.parametrize("n", W.IRREGULAR_LENGTHS)
+def test_irregular_codes(n):
+    H = W.irregular_half(n)
+    assert H.m == n // 2 and H.nnz == 7 * n // 2
+    vd = np.bincount(H.var_degrees(), minlength=7)
+    assert vd[2] == n // 4 and vd[3] == n // 2 and vd[6] == n // 4
+    cd = np.bincount(H.check_degrees(), minlength=9)
+    assert cd[6] == cd[7] == cd[8] == H.m // 3
+    assert len(H.four_cycle_pairs()) == 0
+
+
+def test_codes_are_deterministic():
+    a, b = W.gallager_regular(96, 3, 6, seed=5), W.gallager_regular(96, 3, 6, seed=5)
+    assert np.array_equal(a.col_idx, b.col_idx)
+
+
+def test_gf2_rank():
+    H = W.gallager36(96)
+    r = W.gf2_rank(H)
+    # Gallager blocks each cover every column once, so the dv row-block sums are
+    # equal: rank <= m - (dv - 1).
+    assert r <= H.m - 2
+    Hd = H.dense().astype(np.int64)
+    assert np.linalg.matrix_rank(Hd) >= r  # real rank bounds GF(2) rank
+
+
+def test_awgn_llr_statistics():
+    rng = W.rng_for("stat", 1)
+    for snr in (1.5, 3.0):
+        s2 = float(W.sigma2_for(snr))
+        g = W.awgn_llr(4000, 50, snr, rng).astype(np.float64)
+        assert abs(g.mean() - 2 / s2) < 0.02 * (2 / s2)
+        assert abs(g.var() - 4 / s2) < 0.03 * (4 / s2)
+
+
+def test_bsc_llr():
+    g = W.bsc_llr(1000, 20, 0.05, W.rng_for("bsc"))
+    mag = np.log(0.95 / 0.05)
+    assert np.allclose(np.abs(g), mag, rtol=1e-6)
+    assert abs(np.mean(g < 0) - 0.05) < 0.01
+
+
+def test_serving_trace_rates():
+    codes = [W.gallager36(96), W.gallager36(2640)]
+    tr = W.serving_trace(codes, duration_s=2.0, frames_per_s=5000.0)
+    frames = sum(r.frames for r in tr)
+    assert 0.8 * 10000 < frames < 1.2 * 10000
+    assert all(1 <= r.frames <= 256 for r in tr)
+    assert all(np.diff([r.arrival_s for r in tr]) > 0)

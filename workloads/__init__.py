@@ -1,0 +1,123 @@
+"""Seeded synthetic workloads shared by the oracle tests, the GPU tests and the benchmark.
+
+This package only generates inputs -- parity-check matrices and channel cost
+vectors -- and holds none of the decoder's arithmetic.  The paper's own codes
+(the Margulis [2640,1320] code, the [1057,813] MacKay code and its ensemble of
+100 random n=1002 codes, Sec. 5) are not available here; random codes with the
+same length, rate and degrees stand in for them.
+"""
+from __future__ import annotations
+
+import dataclasses
+import functools
+
+import numpy as np
+
+from .channel import awgn_llr, bsc_llr, sigma2_for
+from .codes import (ParityCheckMatrix, gallager_regular, gf2_rank, irregular, rng_for,
+                    single_check)
+
+__all__ = [
+    "ParityCheckMatrix", "gallager_regular", "irregular", "single_check", "gf2_rank", "rng_for",
+    "awgn_llr", "bsc_llr", "sigma2_for", "PAPER_PARAMS", "gallager36", "gallager48",
+    "irregular_half", "IRREGULAR_LENGTHS", "Batch", "awgn_batch", "mixed_batch",
+    "HEADLINE_SNRS", "serving_trace", "SERVING_LENGTHS",
+]
+
+# Decoder parameters used for every simulation of Sec. 5.1: eps = 1e-5, mu = 3,
+# t_max = 1000, rho = 1.9.
+PAPER_PARAMS = dict(mu=3.0, rho=1.9, max_iter=1000, tol=1e-5)
+
+HEADLINE_SNRS = (1.5, 2.0, 2.5, 3.0)
+IRREGULAR_LENGTHS = (576, 1152, 2304, 4608, 6912, 8064)
+SERVING_LENGTHS = (96, 576, 2640, 8064, 16384)
+
+
+@functools.lru_cache(maxsize=None)
+def gallager36(n: int) -> ParityCheckMatrix:
+    """(3,6)-regular code of length n (fixed seed per n): Gallager's construction when
+    6 divides n, otherwise a random regular socket matching (e.g. n = 16384)."""
+    if n % 6 == 0:
+        return gallager_regular(n, 3, 6, seed=n)
+    return irregular(n, {3: 1.0}, {6: 1.0}, m=n // 2, seed=n)
+
+
+@functools.lru_cache(maxsize=None)
+def gallager48(n: int) -> ParityCheckMatrix:
+    """(4,8)-regular Gallager code of length n (fixed seed per n)."""
+    return gallager_regular(n, 4, 8, seed=n)
+
+
+@functools.lru_cache(maxsize=None)
+def irregular_half(n: int) -> ParityCheckMatrix:
+    """Rate-1/2 irregular code: variable degrees {2:1/4, 3:1/2, 6:1/4}, check degrees
+    {6,7,8} one third each, m = n/2, nnz = 3.5 n."""
+    return irregular(n, {2: 0.25, 3: 0.5, 6: 0.25}, {6: 1 / 3, 7: 1 / 3, 8: 1 / 3}, m=n // 2, seed=n)
+
+
+@dataclasses.dataclass
+class Batch:
+    """Frames to decode.  llr[f] is frame f's FP32 gamma (length n of its code)."""
+
+    codes: list            # list[ParityCheckMatrix]
+    code_of_frame: np.ndarray  # int32 [frames]
+    llr: list              # list of float32 arrays, one per frame (lengths differ across codes)
+    ebn0_db: np.ndarray    # float64 [frames]
+
+    @property
+    def frames(self) -> int:
+        return int(self.code_of_frame.size)
+
+    def flat_llr(self):
+        """(concatenated float32 llr, int64 offsets of each frame)."""
+        lens = np.array([a.size for a in self.llr], dtype=np.int64)
+        off = np.zeros(lens.size, dtype=np.int64)
+        np.cumsum(lens[:-1], out=off[1:])
+        return np.concatenate(self.llr).astype(np.float32), off
+
+
+def awgn_batch(H: ParityCheckMatrix, frames: int, ebn0_db: float, tag: str = "awgn", block: int = 0) -> np.ndarray:
+    """[frames, n] float32 gamma for one code at one Eb/N0 (seeded by code length, SNR and block)."""
+    rng = rng_for(tag, H.n, H.m, int(round(ebn0_db * 1000)), block)
+    return awgn_llr(H.n, frames, ebn0_db, rng)
+
+
+def mixed_batch(codes, frames: int, snr_lo: float, snr_hi: float, tag: str = "mixed", seed: int = 0) -> Batch:
+    """Frames drawn uniformly over `codes`, each with Eb/N0 ~ U[snr_lo, snr_hi]."""
+    rng = rng_for(tag, frames, len(codes), seed)
+    which = rng.integers(len(codes), size=frames).astype(np.int32)
+    snr = rng.uniform(snr_lo, snr_hi, size=frames)
+    llr = []
+    for f in range(frames):
+        H = codes[which[f]]
+        llr.append(awgn_llr(H.n, 1, snr[f], rng)[0])
+    return Batch(list(codes), which, llr, snr)
+
+
+@dataclasses.dataclass
+class Request:
+    arrival_s: float
+    code: int          # index into the serving code list
+    frames: int
+    ebn0_db: float
+    llr: np.ndarray    # float32 [frames, n]
+
+
+def serving_trace(codes, duration_s: float, frames_per_s: float = 50_000.0, max_frames: int = 256,
+                  snr_lo: float = 1.5, snr_hi: float = 3.5, seed: int = 0) -> list:
+    """Poisson arrivals of decode requests: each request carries 1..max_frames frames
+    (uniform) of one code (uniform over `codes`) at one Eb/N0 ~ U[snr_lo, snr_hi]."""
+    rng = rng_for("serving", len(codes), seed)
+    mean_frames = (1 + max_frames) / 2.0
+    rate = frames_per_s / mean_frames  # requests per second
+    t = 0.0
+    out = []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration_s:
+            break
+        c = int(rng.integers(len(codes)))
+        k = int(rng.integers(1, max_frames + 1))
+        snr = float(rng.uniform(snr_lo, snr_hi))
+        out.append(Request(t, c, k, snr, awgn_llr(codes[c].n, k, snr, rng)))
+    return out
