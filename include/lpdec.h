@@ -1,0 +1,168 @@
+/*
+ * lpdec.h -- C ABI of the MI355X (gfx950) ADMM LP decoder.
+ *
+ * Method: Barman, Liu, Draper, Recht, "Decomposition Methods for Large Scale LP
+ * Decoding" (arXiv 1204.0556).  The library solves Feldman's LP relaxation
+ *     minimise gamma^T x  s.t.  P_j x in PP_d for every check j    (eq. feldmanLP)
+ * with the ADMM iteration of Algorithm 1 (Sec. 3.3), over-relaxed as in Sec. 5.2,
+ * each z-update being a Euclidean projection onto the parity polytope PP_d
+ * computed from the two-slice characterisation (Sec. 4, Algorithm 2).
+ *
+ * Conventions for every entry point
+ *   - Return value: LPDEC_OK (0) or a negative lpdec_status; a thread-local
+ *     message for the last failure is available from lpdec_last_error().
+ *   - "host" pointers are read during the call only and stay owned by the caller.
+ *   - "device" pointers are HIP device allocations owned by the caller (e.g. torch
+ *     tensors); they must stay valid until the work queued on `stream` completes.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Decode
+ *     calls are asynchronous on it: outputs are ready when the stream is.
+ *   - Arguments are validated on the host before anything is queued; a rejected
+ *     call queues no work.  Per-frame problems (non-finite LLRs) are reported in
+ *     the frame's flags and never abort the batch.
+ */
+#ifndef LPDEC_H
+#define LPDEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Largest check degree d = |N_c(j)| the kernels support (Sec. 2: the paper's
+ * codes use d = 6 and d = 13; every workload here has d <= 8). */
+#define LPDEC_MAX_CHECK_DEGREE 8
+
+typedef enum {
+    LPDEC_OK = 0,
+    LPDEC_EINVAL = -1,       /* malformed argument (message says which)            */
+    LPDEC_ENOMEM = -2,       /* a device or host allocation failed                 */
+    LPDEC_EDEVICE = -3,      /* a HIP runtime call failed                          */
+    LPDEC_EUNSUPPORTED = -4, /* valid input outside the supported envelope         */
+    LPDEC_EBUSY = -5         /* resource in use (serving queue full)               */
+} lpdec_status;
+
+/* Per-frame flag bits written to flags_out. */
+#define LPDEC_FLAG_CONVERGED 0x01u /* both residuals fell below tol (Alg. 1 UNTIL)     */
+#define LPDEC_FLAG_INTEGRAL 0x02u  /* max_i min(x_i, 1 - x_i) <= 1e-3                   */
+#define LPDEC_FLAG_CODEWORD 0x04u  /* H xhat = 0 (mod 2), xhat_i = [x_i >= 1/2]         */
+#define LPDEC_FLAG_CERTIFIED 0x08u /* converged, integral and a codeword: the LP optimum
+                                      is integral, hence the ML codeword (Sec. 1)       */
+#define LPDEC_FLAG_INVALID 0x80u   /* a non-finite LLR: frame not decoded, x = 1/2      */
+
+/* Message storage precision for the state kept in HBM between iterations. */
+#define LPDEC_STORAGE_FP32 0
+#define LPDEC_STORAGE_FP16 1 /* z and u = lambda/mu stored as FP16, FP32 compute     */
+
+/* Execution form. */
+#define LPDEC_MODE_AUTO 0     /* fastest form that fits the code                       */
+#define LPDEC_MODE_RESIDENT 1 /* one persistent launch; a workgroup keeps a frame's
+                                 replicas and duals in registers until it converges    */
+#define LPDEC_MODE_STREAMED 2 /* replicas and duals live in HBM; one launch per
+                                 iteration over all unfinished frames                  */
+#define LPDEC_MODE_PERSISTENT_GLOBAL 3 /* one persistent launch; per-workgroup state in
+                                 global memory (codes too large for registers)         */
+
+typedef struct lpdec_code lpdec_code; /* opaque; holds the device copy of H */
+
+typedef struct {
+    float mu;         /* ADMM penalty, > 0 (the paper uses 3, Sec. 5.1)                  */
+    float rho;        /* over-relaxation, 1 <= rho < 2 (the paper uses 1.9, Sec. 5.2);
+                         rho = 1 is Algorithm 1 exactly                                   */
+    int32_t max_iter; /* >= 1 (t_max; 1000 in Sec. 5.1)                                   */
+    float tol;        /* epsilon >= 0 (1e-5 in Sec. 5.1); 0 disables the stopping test   */
+    int32_t storage;  /* LPDEC_STORAGE_*; FP16 applies to the STREAMED form only          */
+    int32_t mode;     /* LPDEC_MODE_*                                                     */
+} lpdec_params;
+
+/* Paper defaults: mu = 3, rho = 1.9, max_iter = 1000, tol = 1e-5, FP32, AUTO. */
+lpdec_params lpdec_default_params(void);
+
+/* Build a decoder for the code with parity-check matrix H (Sec. 2).
+ *   m, n      number of checks (rows) and variables (columns), both >= 1
+ *   nnz       number of ones in H (edges of the Tanner graph)
+ *   row_ptr   host [m+1], CSR row pointers, row_ptr[0] = 0, row_ptr[m] = nnz
+ *   col_idx   host [nnz], column indices, strictly increasing within a row
+ * Every column must appear in some row (x_i is an average over |N_v(i)| > 0
+ * replicas, Sec. 3.2) and every row must have degree 2..LPDEC_MAX_CHECK_DEGREE.
+ * The matrix is copied to the device; the caller keeps ownership of its arrays.
+ * Errors: LPDEC_EINVAL (malformed CSR, empty column, duplicate index, row of
+ * degree < 2), LPDEC_EUNSUPPORTED (degree above the maximum), LPDEC_ENOMEM,
+ * LPDEC_EDEVICE.  On error *out is set to NULL. */
+lpdec_status lpdec_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
+                               const int32_t *col_idx, lpdec_code **out);
+
+/* Release a code and its cached workspaces; waits for work queued on it.  NULL-safe. */
+void lpdec_code_destroy(lpdec_code *code);
+
+typedef struct {
+    int32_t m, n;
+    int64_t nnz;
+    int32_t min_check_degree, max_check_degree;
+    int32_t resident_capable; /* 1 if LPDEC_MODE_RESIDENT fits this code               */
+    int32_t threads_per_frame;/* workgroup size the decode kernels use for this code     */
+} lpdec_code_info;
+
+lpdec_status lpdec_code_get_info(const lpdec_code *code, lpdec_code_info *info);
+
+/* Decode `batch` independent frames (Algorithm 1).
+ *   llr       device [batch*n] FP32, row-major; gamma_i = log W(y_i|0)/W(y_i|1)
+ *             (Sec. 2), e.g. 2 y_i / sigma^2 for BPSK (0 -> +1) over AWGN
+ *   p         host; NULL means lpdec_default_params()
+ *   x_out     device [batch*n] FP32: the final x in [0,1]^n (the x of the last
+ *             iteration run)
+ *   iters_out device [batch] int32: iterations run (max_iter if not converged, 0 if invalid)
+ *   flags_out device [batch] uint8: LPDEC_FLAG_* bits
+ * batch = 0 is a no-op.  The call is asynchronous on `stream`.  Errors:
+ * LPDEC_EINVAL (bad parameters or NULL pointers), LPDEC_EUNSUPPORTED (mode not
+ * available for this code), LPDEC_ENOMEM (workspace), LPDEC_EDEVICE. */
+lpdec_status lpdec_decode(const lpdec_code *code, int32_t batch, const float *llr,
+                          const lpdec_params *p, float *x_out, int32_t *iters_out,
+                          uint8_t *flags_out, void *stream);
+
+/* lpdec_decode with access to the ADMM state, for checkpoint/resume and for
+ * comparing messages after a fixed number of iterations.
+ *   z_state, u_state  device [batch*nnz] FP32 in the CSR edge order of H: the
+ *             replicas z_j and scaled duals u_j = lambda_j / mu (Sec. 3.4).  Either
+ *             both NULL or both given.
+ *   state_flags  bit0 LPDEC_STATE_IN: start from the given state instead of zero;
+ *                bit1 LPDEC_STATE_OUT: write the final state back.
+ * Resuming a run for K2 iterations from the state after K1 reproduces K1+K2
+ * iterations exactly when stopping is disabled (tol = 0). */
+#define LPDEC_STATE_IN 0x1
+#define LPDEC_STATE_OUT 0x2
+lpdec_status lpdec_decode_state(const lpdec_code *code, int32_t batch, const float *llr,
+                                const lpdec_params *p, float *x_out, int32_t *iters_out,
+                                uint8_t *flags_out, float *z_state, float *u_state,
+                                int32_t state_flags, void *stream);
+
+/* Batched uneven decoding: `nframes` frames drawn from `ncodes` codes, decoded in
+ * one persistent launch with per-frame early termination.
+ *   codes          host [ncodes] code handles
+ *   code_of_frame  host [nframes], values in [0, ncodes)
+ *   llr_offset     host [nframes] int64: frame f's LLRs are llr[llr_offset[f] ...
+ *                  + n(code) - 1] in the device array `llr`
+ *   x_offset       host [nframes] int64: frame f's x goes to x_out[x_offset[f] ...]
+ *   iters_out, flags_out  device [nframes]
+ * Offsets are checked against llr_len / x_len (elements).  A frame's result does
+ * not depend on the other frames of the batch. */
+lpdec_status lpdec_decode_multi(const lpdec_code *const *codes, int32_t ncodes, int32_t nframes,
+                                const int32_t *code_of_frame, const int64_t *llr_offset,
+                                const float *llr, int64_t llr_len, const lpdec_params *p,
+                                float *x_out, const int64_t *x_offset, int64_t x_len,
+                                int32_t *iters_out, uint8_t *flags_out, void *stream);
+
+/* The check-node operation alone: z_k = Pi_PPd(v_k) for `count` vectors of
+ * degree d (2 <= d <= LPDEC_MAX_CHECK_DEGREE), Algorithm 2 / Sec. 4.4.
+ *   v, z  device [count*d] FP32, row-major (z may not alias v). */
+lpdec_status lpdec_project(int32_t d, int32_t count, const float *v, float *z, void *stream);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *lpdec_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPDEC_H */

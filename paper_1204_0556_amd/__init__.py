@@ -1,0 +1,245 @@
+"""MI355X ADMM LP decoder (arXiv 1204.0556) -- Python binding of liblpdec.so.
+
+Every step of the decoder runs in the HIP library; this module only marshals
+arguments through the C ABI declared in include/lpdec.h.  PyTorch supplies
+device memory and streams.  If the library is missing the import fails: there
+is no CPU fallback.
+
+    import paper_1204_0556_amd as lp
+    code = lp.Code(m, n, row_ptr, col_idx)          # H as CSR over checks
+    x, iters, flags = lp.decode(code, llr)           # llr: float32 [B, n] on cuda
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "Code", "decode", "decode_state", "decode_multi", "project", "default_params", "last_error",
+    "LpdecError", "FLAG_CONVERGED", "FLAG_INTEGRAL", "FLAG_CODEWORD", "FLAG_CERTIFIED", "FLAG_INVALID",
+    "MODE_AUTO", "MODE_RESIDENT", "MODE_STREAMED", "MODE_PERSISTENT_GLOBAL", "STORAGE_FP32", "STORAGE_FP16",
+    "MAX_CHECK_DEGREE", "library_path",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "liblpdec.so")
+
+FLAG_CONVERGED, FLAG_INTEGRAL, FLAG_CODEWORD, FLAG_CERTIFIED, FLAG_INVALID = 0x01, 0x02, 0x04, 0x08, 0x80
+MODE_AUTO, MODE_RESIDENT, MODE_STREAMED, MODE_PERSISTENT_GLOBAL = 0, 1, 2, 3
+STORAGE_FP32, STORAGE_FP16 = 0, 1
+STATE_IN, STATE_OUT = 0x1, 0x2
+MAX_CHECK_DEGREE = 8
+
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED", -5: "EBUSY"}
+
+
+class LpdecError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"lpdec {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_float), ("rho", ctypes.c_float), ("max_iter", ctypes.c_int32),
+                ("tol", ctypes.c_float), ("storage", ctypes.c_int32), ("mode", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("min_check_degree", ctypes.c_int32), ("max_check_degree", ctypes.c_int32),
+                ("resident_capable", ctypes.c_int32), ("threads_per_frame", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(library_path):
+        raise ImportError(f"{library_path} is missing: build it with paper_1204_0556_amd/build.py "
+                          "(python -c 'import __graft_entry__; __graft_entry__.build()')")
+    lib = ctypes.CDLL(library_path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    P = ctypes.POINTER
+    lib.lpdec_default_params.restype = _Params
+    lib.lpdec_last_error.restype = ctypes.c_char_p
+    lib.lpdec_code_create.argtypes = [i32, i32, i64, P(i32), P(i32), P(vp)]
+    lib.lpdec_code_create.restype = ctypes.c_int
+    lib.lpdec_code_destroy.argtypes = [vp]
+    lib.lpdec_code_destroy.restype = None
+    lib.lpdec_code_get_info.argtypes = [vp, P(_Info)]
+    lib.lpdec_code_get_info.restype = ctypes.c_int
+    lib.lpdec_decode.argtypes = [vp, i32, vp, P(_Params), vp, vp, vp, vp]
+    lib.lpdec_decode.restype = ctypes.c_int
+    lib.lpdec_decode_state.argtypes = [vp, i32, vp, P(_Params), vp, vp, vp, vp, vp, i32, vp]
+    lib.lpdec_decode_state.restype = ctypes.c_int
+    lib.lpdec_decode_multi.argtypes = [P(vp), i32, i32, P(i32), P(i64), vp, i64, P(_Params), vp, P(i64), i64,
+                                       vp, vp, vp]
+    lib.lpdec_decode_multi.restype = ctypes.c_int
+    lib.lpdec_project.argtypes = [i32, i32, vp, vp, vp]
+    lib.lpdec_project.restype = ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def last_error() -> str:
+    return _lib.lpdec_last_error().decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise LpdecError(status, last_error())
+
+
+def default_params() -> dict:
+    p = _lib.lpdec_default_params()
+    return {k: getattr(p, k) for k, _ in _Params._fields_}
+
+
+def _params(mu=None, rho=None, max_iter=None, tol=None, storage=None, mode=None) -> _Params:
+    p = _lib.lpdec_default_params()
+    if mu is not None: p.mu = float(mu)
+    if rho is not None: p.rho = float(rho)
+    if max_iter is not None: p.max_iter = int(max_iter)
+    if tol is not None: p.tol = float(tol)
+    if storage is not None: p.storage = int(storage)
+    if mode is not None: p.mode = int(mode)
+    return p
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Code:
+    """A parity-check matrix H resident on the current device (lpdec_code_create)."""
+
+    def __init__(self, m, n=None, row_ptr=None, col_idx=None):
+        if n is None:  # a ParityCheckMatrix-like object
+            H = m
+            m, n, row_ptr, col_idx = H.m, H.n, H.row_ptr, H.col_idx
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        if rp.size != m + 1:
+            raise ValueError("row_ptr must have m+1 entries")
+        h = ctypes.c_void_p()
+        _check(_lib.lpdec_code_create(int(m), int(n), int(ci.size),
+                                      rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      ci.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(h)))
+        self._h = h
+        self.m, self.n, self.nnz = int(m), int(n), int(ci.size)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("code is closed")
+        return self._h
+
+    @property
+    def info(self) -> dict:
+        inf = _Info()
+        _check(_lib.lpdec_code_get_info(self.handle, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    def close(self):
+        if self._h:
+            _lib.lpdec_code_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def decode(code: Code, llr, out=None, stream=None, **params):
+    """Decode llr (float32 [B, n] CUDA tensor).  Returns (x [B,n] f32, iters [B] i32, flags [B] u8)."""
+    torch = _torch()
+    B = int(llr.shape[0]) if llr.dim() == 2 else 1
+    if llr.numel() != B * code.n:
+        raise ValueError("llr must be [batch, n]")
+    if out is None:
+        out = (torch.empty((B, code.n), dtype=torch.float32, device=llr.device),
+               torch.empty(B, dtype=torch.int32, device=llr.device),
+               torch.empty(B, dtype=torch.uint8, device=llr.device))
+    x, it, fl = out
+    p = _params(**params)
+    _check(_lib.lpdec_decode(code.handle, B, _dev_ptr(llr, torch.float32, "llr"), ctypes.byref(p),
+                             _dev_ptr(x, torch.float32, "x"), _dev_ptr(it, torch.int32, "iters"),
+                             _dev_ptr(fl, torch.uint8, "flags"), _stream(stream)))
+    return x, it, fl
+
+
+def decode_state(code: Code, llr, z=None, u=None, state_in=False, state_out=True, stream=None, **params):
+    """Decode with the ADMM state (z, u = lambda/mu) in CSR edge order, [B, nnz] float32.
+    Returns (x, iters, flags, z, u)."""
+    torch = _torch()
+    B = int(llr.shape[0])
+    dev = llr.device
+    if z is None:
+        z = torch.zeros((B, code.nnz), dtype=torch.float32, device=dev)
+    if u is None:
+        u = torch.zeros((B, code.nnz), dtype=torch.float32, device=dev)
+    x = torch.empty((B, code.n), dtype=torch.float32, device=dev)
+    it = torch.empty(B, dtype=torch.int32, device=dev)
+    fl = torch.empty(B, dtype=torch.uint8, device=dev)
+    flags = (STATE_IN if state_in else 0) | (STATE_OUT if state_out else 0)
+    p = _params(**params)
+    _check(_lib.lpdec_decode_state(code.handle, B, _dev_ptr(llr, torch.float32, "llr"), ctypes.byref(p),
+                                   _dev_ptr(x, torch.float32, "x"), _dev_ptr(it, torch.int32, "iters"),
+                                   _dev_ptr(fl, torch.uint8, "flags"), _dev_ptr(z, torch.float32, "z"),
+                                   _dev_ptr(u, torch.float32, "u"), flags, _stream(stream)))
+    return x, it, fl, z, u
+
+
+def decode_multi(codes, code_of_frame, llr_offset, llr, x_offset, x_len, stream=None, **params):
+    """Frames of several codes in one persistent launch.  code_of_frame, llr_offset,
+    x_offset are host int arrays; llr is a flat float32 CUDA tensor.
+    Returns (x_flat [x_len], iters [F], flags [F])."""
+    torch = _torch()
+    cof = np.ascontiguousarray(code_of_frame, dtype=np.int32)
+    lo = np.ascontiguousarray(llr_offset, dtype=np.int64)
+    xo = np.ascontiguousarray(x_offset, dtype=np.int64)
+    F = int(cof.size)
+    dev = llr.device
+    x = torch.empty(int(x_len), dtype=torch.float32, device=dev)
+    it = torch.empty(F, dtype=torch.int32, device=dev)
+    fl = torch.empty(F, dtype=torch.uint8, device=dev)
+    handles = (ctypes.c_void_p * len(codes))(*[c.handle.value for c in codes])
+    p = _params(**params)
+    _check(_lib.lpdec_decode_multi(handles, len(codes), F, cof.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   lo.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   _dev_ptr(llr, torch.float32, "llr"), int(llr.numel()), ctypes.byref(p),
+                                   _dev_ptr(x, torch.float32, "x"),
+                                   xo.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(x_len),
+                                   _dev_ptr(it, torch.int32, "iters"), _dev_ptr(fl, torch.uint8, "flags"),
+                                   _stream(stream)))
+    return x, it, fl
+
+
+def project(v, stream=None):
+    """Pi_PPd row-wise for v float32 [count, d] (CUDA)."""
+    torch = _torch()
+    count, d = int(v.shape[0]), int(v.shape[1])
+    z = torch.empty_like(v)
+    _check(_lib.lpdec_project(d, count, _dev_ptr(v, torch.float32, "v"), _dev_ptr(z, torch.float32, "z"),
+                              _stream(stream)))
+    return z

@@ -1,0 +1,681 @@
+// Host runtime of the MI355X ADMM LP decoder: code validation and layout
+// planning, device upload, workspace management and the C ABI of lpdec.h.
+//
+// The layout plan (see DevCode in lpdec_internal.h) is what makes the kernels
+// coalesced and register-resident:
+//   * checks are grouped by degree into chunks of 64, one check per wave lane,
+//     with edge state stored lane-minor inside a chunk;
+//   * variables are renumbered by decreasing degree so that a variable's replicas
+//     form one contiguous slot block (its CSC block), summed in a fixed order;
+//   * chunk c belongs to wave c % waves, so a workgroup of `waves` wavefronts
+//     covers one frame and each wave owns `cpt` chunks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/lpdec.h"
+#include "lpdec_internal.h"
+
+using namespace lpdec;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lpdec_status fail(lpdec_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t _e = (expr);                                                                \
+        if (_e != hipSuccess)                                                                  \
+            return fail(LPDEC_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(_e));        \
+    } while (0)
+
+// Device properties, queried once per device.
+struct DeviceInfo {
+    int device = -1;
+    int cus = 0;
+    size_t max_lds = 0;
+};
+
+DeviceInfo device_info() {
+    DeviceInfo di;
+    if (hipGetDevice(&di.device) != hipSuccess) return di;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, di.device) != hipSuccess) return di;
+    di.cus = prop.multiProcessorCount;
+    di.max_lds = prop.sharedMemPerBlock;
+    // gfx950 exposes 160 KB of LDS per workgroup.
+    if (prop.maxSharedMemoryPerMultiProcessor > di.max_lds) di.max_lds = prop.maxSharedMemoryPerMultiProcessor;
+    return di;
+}
+
+template <typename T>
+hipError_t upload(const std::vector<T> &h, T **d) {
+    *d = nullptr;
+    if (h.empty()) return hipSuccess;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(d), h.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// Reusable device buffer that only grows.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t need) {
+        if (need <= bytes) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess) return e;
+            p = nullptr;
+            bytes = 0;
+        }
+        need = std::max<size_t>(need, 256);
+        hipError_t e = hipMalloc(&p, need);
+        if (e == hipSuccess) bytes = need;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+}  // namespace
+
+// Workspace for one decode call; serialised across streams with an event.
+struct Workspace {
+    std::mutex mu;
+    hipEvent_t last = nullptr;
+    DevBuf queue;      // persistent work counter
+    DevBuf codes;      // DevCode array (multi-code launches)
+    DevBuf frame_meta; // code_of_frame / offsets
+    DevBuf z, u, st, active, gslots, gstate;
+    int *host_active = nullptr; // pinned
+    ~Workspace() {
+        queue.release(); codes.release(); frame_meta.release();
+        z.release(); u.release(); st.release(); active.release(); gslots.release(); gstate.release();
+        if (host_active) (void)hipHostFree(host_active);
+        if (last) (void)hipEventDestroy(last);
+    }
+};
+
+struct lpdec_code {
+    DevCode dc{};          // host copy with device pointers
+    DevCode *d_dc = nullptr;
+    std::vector<void *> allocs;
+    int device = -1;
+    bool resident_ok = false;
+    LaunchConfig resident_cfg{};
+    Workspace ws;
+    ~lpdec_code() {
+        if (d_dc) (void)hipFree(d_dc);
+        for (void *p : allocs) (void)hipFree(p);
+    }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Validation and layout planning.
+
+lpdec_status build_plan(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                        lpdec_code *code) {
+    if (m < 1 || n < 1) return fail(LPDEC_EINVAL, "m and n must be >= 1 (got m=%d n=%d)", m, n);
+    if (!row_ptr || !col_idx) return fail(LPDEC_EINVAL, "row_ptr and col_idx must not be NULL");
+    if (nnz < 1 || row_ptr[0] != 0 || row_ptr[m] != nnz)
+        return fail(LPDEC_EINVAL, "row_ptr must start at 0 and end at nnz=%lld", (long long)nnz);
+    if (n > 65536 || nnz > 65536)
+        return fail(LPDEC_EUNSUPPORTED, "codes with n > 65536 or nnz > 65536 are not supported (n=%d nnz=%lld)", n,
+                    (long long)nnz);
+    std::vector<int> vdeg(n, 0);
+    int dmin = 1 << 30, dmax = 0;
+    for (int j = 0; j < m; ++j) {
+        const int d = row_ptr[j + 1] - row_ptr[j];
+        if (d < 0) return fail(LPDEC_EINVAL, "row_ptr decreases at row %d", j);
+        if (row_ptr[j + 1] > nnz) return fail(LPDEC_EINVAL, "row_ptr[%d] exceeds nnz", j + 1);
+        if (d < 2) return fail(LPDEC_EINVAL, "row %d has degree %d; checks need degree >= 2", j, d);
+        if (d > LPDEC_MAX_CHECK_DEGREE)
+            return fail(LPDEC_EUNSUPPORTED, "row %d has degree %d > %d", j, d, LPDEC_MAX_CHECK_DEGREE);
+        dmin = std::min(dmin, d);
+        dmax = std::max(dmax, d);
+        for (int e = row_ptr[j]; e < row_ptr[j + 1]; ++e) {
+            const int c = col_idx[e];
+            if (c < 0 || c >= n) return fail(LPDEC_EINVAL, "column index %d out of range in row %d", c, j);
+            if (e > row_ptr[j] && c <= col_idx[e - 1])
+                return fail(LPDEC_EINVAL, "row %d: column indices must be strictly increasing", j);
+            vdeg[c]++;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        if (vdeg[i] == 0) return fail(LPDEC_EINVAL, "column %d has no checks (empty column of H)", i);
+
+    // variables: stable order by decreasing degree
+    std::vector<int> vorder(n);
+    std::iota(vorder.begin(), vorder.end(), 0);
+    std::stable_sort(vorder.begin(), vorder.end(), [&](int a, int b) { return vdeg[a] > vdeg[b]; });
+    std::vector<int> vint(n);
+    for (int i = 0; i < n; ++i) vint[vorder[i]] = i;
+    DevCode &D = code->dc;
+    D.m = m;
+    D.n = n;
+    D.E = (int)nnz;
+    D.dmin = dmin;
+    D.dmax = dmax;
+    D.var_identity = 1;
+    for (int i = 0; i < n; ++i)
+        if (vorder[i] != i) D.var_identity = 0;
+    // degree classes
+    D.nvc = 0;
+    int slot = 0;
+    for (int i = 0; i < n; ++i) {
+        const int d = vdeg[vorder[i]];
+        if (D.nvc == 0 || D.vc_deg[D.nvc - 1] != d) {
+            if (D.nvc == 8) return fail(LPDEC_EUNSUPPORTED, "more than 8 distinct variable degrees");
+            D.vc_start[D.nvc] = i;
+            D.vc_slot0[D.nvc] = slot;
+            D.vc_deg[D.nvc] = d;
+            D.vc_inv[D.nvc] = 1.0f / (float)d;
+            D.nvc++;
+        }
+        slot += d;
+    }
+    for (int c = D.nvc; c <= 8; ++c) D.vc_start[c] = n;
+    for (int c = D.nvc; c < 8; ++c) {
+        D.vc_slot0[c] = slot;
+        D.vc_deg[c] = 1;
+        D.vc_inv[c] = 1.0f;
+    }
+    // slot of every CSR edge: variable blocks in internal order, edges ascending
+    std::vector<int> vstart(n + 1, 0);
+    for (int i = 0; i < n; ++i) vstart[i + 1] = vstart[i] + vdeg[vorder[i]];
+    std::vector<int> fill(vstart.begin(), vstart.end() - 1);
+    std::vector<int> eslot(nnz);
+    for (int j = 0; j < m; ++j)
+        for (int e = row_ptr[j]; e < row_ptr[j + 1]; ++e) eslot[e] = fill[vint[col_idx[e]]]++;
+
+    // checks grouped by degree (stable), chunks of 64
+    std::vector<int> corder(m);
+    std::iota(corder.begin(), corder.end(), 0);
+    std::stable_sort(corder.begin(), corder.end(), [&](int a, int b) {
+        return (row_ptr[a + 1] - row_ptr[a]) < (row_ptr[b + 1] - row_ptr[b]);
+    });
+    std::vector<int> chunk_deg, chunk_off, chunk_cnt;
+    std::vector<uint32_t> meta;
+    std::vector<int> ecsr;
+    int pos = 0;
+    while (pos < m) {
+        const int d = row_ptr[corder[pos] + 1] - row_ptr[corder[pos]];
+        int cnt = 0;
+        while (pos + cnt < m && cnt < kWave && (row_ptr[corder[pos + cnt] + 1] - row_ptr[corder[pos + cnt]]) == d)
+            ++cnt;
+        const int off = (int)meta.size();
+        chunk_deg.push_back(d);
+        chunk_off.push_back(off);
+        chunk_cnt.push_back(cnt);
+        meta.resize(off + (size_t)d * kWave, 0u);
+        ecsr.resize(off + (size_t)d * kWave, -1);
+        for (int l = 0; l < cnt; ++l) {
+            const int j = corder[pos + l];
+            for (int k = 0; k < d; ++k) {
+                const int e = row_ptr[j] + k;
+                meta[off + k * kWave + l] = ((uint32_t)eslot[e] << 16) | (uint32_t)vint[col_idx[e]];
+                ecsr[off + k * kWave + l] = e;
+            }
+        }
+        pos += cnt;
+    }
+    D.nchunks = (int)chunk_deg.size();
+    D.E_int = (int)meta.size();
+    // waves: as many as possible up to 16 per workgroup (fewer chunks per wave)
+    D.cpt = (D.nchunks + kMaxWaves - 1) / kMaxWaves;
+    D.waves = (D.nchunks + D.cpt - 1) / D.cpt;
+
+    int *d_cdeg, *d_coff, *d_ccnt, *d_ecsr, *d_vorig;
+    uint32_t *d_meta;
+    hipError_t e = hipGetDevice(&code->device);
+    if (e != hipSuccess) return fail(LPDEC_EDEVICE, "no HIP device: %s", hipGetErrorString(e));
+    if ((e = upload(chunk_deg, &d_cdeg)) != hipSuccess ||
+        (code->allocs.push_back(d_cdeg), (e = upload(chunk_off, &d_coff)) != hipSuccess) ||
+        (code->allocs.push_back(d_coff), (e = upload(chunk_cnt, &d_ccnt)) != hipSuccess) ||
+        (code->allocs.push_back(d_ccnt), (e = upload(meta, &d_meta)) != hipSuccess) ||
+        (code->allocs.push_back(d_meta), (e = upload(ecsr, &d_ecsr)) != hipSuccess) ||
+        (code->allocs.push_back(d_ecsr), (e = upload(vorder, &d_vorig)) != hipSuccess))
+        return fail(e == hipErrorOutOfMemory ? LPDEC_ENOMEM : LPDEC_EDEVICE, "uploading the code: %s",
+                    hipGetErrorString(e));
+    code->allocs.push_back(d_vorig);
+    D.chunk_deg = d_cdeg;
+    D.chunk_off = d_coff;
+    D.chunk_cnt = d_ccnt;
+    D.edge_meta = d_meta;
+    D.edge_csr = d_ecsr;
+    D.var_orig = d_vorig;
+    if ((e = hipMalloc(&code->d_dc, sizeof(DevCode))) != hipSuccess)
+        return fail(LPDEC_ENOMEM, "allocating the code descriptor: %s", hipGetErrorString(e));
+    if ((e = hipMemcpy(code->d_dc, &D, sizeof(DevCode), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(LPDEC_EDEVICE, "uploading the code descriptor: %s", hipGetErrorString(e));
+    return LPDEC_OK;
+}
+
+// Launch-shape planning for a set of codes decoded together.
+struct Shape {
+    int waves = 0, cpt = 0, nmax = 0, Emax = 0, Eint_max = 0, dclass = 0;
+};
+
+Shape shape_of(const lpdec_code *const *codes, int ncodes) {
+    Shape s;
+    bool all6 = true;
+    for (int c = 0; c < ncodes; ++c) {
+        const DevCode &D = codes[c]->dc;
+        s.waves = std::max(s.waves, D.waves);
+        s.cpt = std::max(s.cpt, D.cpt);
+        s.nmax = std::max(s.nmax, D.n);
+        s.Emax = std::max(s.Emax, D.E);
+        s.Eint_max = std::max(s.Eint_max, D.E_int);
+        all6 = all6 && D.dmin == 6 && D.dmax == 6;
+    }
+    s.dclass = all6 ? 0 : 1;
+    return s;
+}
+
+constexpr size_t kStaticLds = 1024;  // s_red + s_frame + alignment
+constexpr size_t kLdsLimit = 160 * 1024;
+
+// Resident form: z,u in registers (cpt <= 2 chunks per wave, DMAX = 6) and
+// gamma/mu of <= 8 variables per thread; slots and x in LDS.
+bool resident_config(const Shape &s, LaunchConfig *cfg) {
+    if (s.dclass != 0) return false;  // register budget only holds for degree-6 codes
+    if (s.cpt > 2) return false;
+    const int threads = s.waves * kWave;
+    if (threads > 768) return false;
+    const int vpt = (s.nmax + threads - 1) / threads;
+    if (vpt > 8) return false;
+    const size_t lds = 4 * ((size_t)s.Emax + s.nmax);
+    if (lds + kStaticLds > kLdsLimit) return false;
+    cfg->form = Form::Resident;
+    cfg->cpt_tmpl = 2;
+    cfg->vpt_tmpl = vpt <= 4 ? 4 : 8;
+    cfg->dclass = 0;
+    cfg->lds_slots = true;
+    cfg->half = false;
+    cfg->threads = threads;
+    cfg->lds_bytes = lds;
+    cfg->lds_E = s.Emax;
+    cfg->slot_stride = 0;
+    cfg->state_stride = 0;
+    return true;
+}
+
+void persistent_global_config(const Shape &s, LaunchConfig *cfg) {
+    const size_t lds_all = 4 * ((size_t)s.Emax + s.nmax);
+    cfg->form = Form::PersistentGlobal;
+    cfg->cpt_tmpl = 0;
+    cfg->vpt_tmpl = 0;
+    cfg->dclass = s.dclass;
+    cfg->lds_slots = lds_all + kStaticLds <= kLdsLimit;
+    cfg->half = false;
+    cfg->threads = s.waves * kWave;
+    cfg->lds_bytes = cfg->lds_slots ? lds_all : 4 * (size_t)s.nmax;
+    cfg->lds_E = s.Emax;
+    cfg->slot_stride = s.Emax;
+    cfg->state_stride = s.Eint_max;
+}
+
+void streamed_config(const Shape &s, bool half, LaunchConfig *cfg) {
+    const size_t lds_all = 4 * ((size_t)s.Emax + s.nmax);
+    cfg->form = Form::Streamed;
+    cfg->lds_slots = lds_all + kStaticLds <= kLdsLimit;
+    cfg->cpt_tmpl = (cfg->lds_slots && s.cpt <= 2) ? 2 : 0;
+    cfg->vpt_tmpl = 0;
+    cfg->dclass = s.dclass;
+    cfg->half = half;
+    cfg->threads = s.waves * kWave;
+    cfg->lds_bytes = cfg->lds_slots ? lds_all : 4 * (size_t)s.nmax;
+    cfg->lds_E = s.Emax;
+    cfg->slot_stride = s.Emax;
+    cfg->state_stride = 0;
+}
+
+int occupancy_grid(const LaunchConfig &cfg, int frames) {
+    DeviceInfo di = device_info();
+    const int cus = di.cus > 0 ? di.cus : 256;
+    int per_cu = 0;
+    if (decode_occupancy(cfg, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+    return std::max(1, std::min(frames, cus * per_cu));
+}
+
+lpdec_status check_params(const lpdec_params *p) {
+    if (!(p->mu > 0.0f) || !std::isfinite(p->mu)) return fail(LPDEC_EINVAL, "mu must be a positive finite number");
+    if (!(p->rho > 0.0f && p->rho < 2.0f)) return fail(LPDEC_EINVAL, "rho must lie in (0, 2)");
+    if (p->max_iter < 1) return fail(LPDEC_EINVAL, "max_iter must be >= 1");
+    if (!(p->tol >= 0.0f) || !std::isfinite(p->tol)) return fail(LPDEC_EINVAL, "tol must be finite and >= 0");
+    if (p->storage != LPDEC_STORAGE_FP32 && p->storage != LPDEC_STORAGE_FP16)
+        return fail(LPDEC_EINVAL, "unknown storage %d", p->storage);
+    if (p->mode < LPDEC_MODE_AUTO || p->mode > LPDEC_MODE_PERSISTENT_GLOBAL)
+        return fail(LPDEC_EINVAL, "unknown mode %d", p->mode);
+    return LPDEC_OK;
+}
+
+// Acquire the workspace of the call's (first) code for exclusive use on `stream`.
+struct WsGuard {
+    Workspace &ws;
+    hipStream_t stream;
+    std::unique_lock<std::mutex> lk;
+    WsGuard(Workspace &w, hipStream_t s) : ws(w), stream(s), lk(w.mu) {
+        if (ws.last) (void)hipStreamWaitEvent(stream, ws.last, 0);
+    }
+    ~WsGuard() { (void)done(); }
+    hipError_t done() {
+        if (!ws.last) {
+            hipError_t e = hipEventCreateWithFlags(&ws.last, hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        return hipEventRecord(ws.last, stream);
+    }
+};
+
+// Core decode over a set of codes.  frames' code ids / offsets are either null
+// (single code, dense layout) or host arrays staged into the workspace.
+lpdec_status decode_core(const lpdec_code *const *codes, int ncodes, int nframes, const int32_t *code_of_frame,
+                         const int64_t *llr_off, const int64_t *x_off, const float *llr, const lpdec_params *pin,
+                         float *x_out, int32_t *iters_out, uint8_t *flags_out, float *z_state, float *u_state,
+                         int state_flags, void *stream_v) {
+    lpdec_params p = pin ? *pin : lpdec_default_params();
+    lpdec_status st = check_params(&p);
+    if (st != LPDEC_OK) return st;
+    if (nframes < 0) return fail(LPDEC_EINVAL, "batch must be >= 0");
+    if (nframes == 0) return LPDEC_OK;
+    if (!llr || !x_out || !iters_out || !flags_out)
+        return fail(LPDEC_EINVAL, "llr, x_out, iters_out and flags_out must not be NULL");
+    if ((z_state == nullptr) != (u_state == nullptr))
+        return fail(LPDEC_EINVAL, "z_state and u_state must both be given or both be NULL");
+    if (state_flags && !z_state) return fail(LPDEC_EINVAL, "state_flags given without state arrays");
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    lpdec_code *c0 = const_cast<lpdec_code *>(codes[0]);
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    for (int c = 0; c < ncodes; ++c)
+        if (codes[c]->device != dev)
+            return fail(LPDEC_EINVAL, "code %d was created on device %d, current device is %d", c, codes[c]->device,
+                        dev);
+
+    const Shape s = shape_of(codes, ncodes);
+    LaunchConfig cfg{};
+    const bool half = p.storage == LPDEC_STORAGE_FP16;
+    int mode = p.mode;
+    if (half && mode != LPDEC_MODE_STREAMED && mode != LPDEC_MODE_AUTO)
+        return fail(LPDEC_EUNSUPPORTED, "FP16 storage applies to the streamed form only");
+    if (mode == LPDEC_MODE_AUTO) mode = half ? LPDEC_MODE_STREAMED : LPDEC_MODE_RESIDENT;
+    if (mode == LPDEC_MODE_RESIDENT && !resident_config(s, &cfg)) {
+        if (p.mode == LPDEC_MODE_RESIDENT)
+            return fail(LPDEC_EUNSUPPORTED, "the register-resident form does not fit this code");
+        mode = LPDEC_MODE_PERSISTENT_GLOBAL;
+    }
+    if (mode == LPDEC_MODE_PERSISTENT_GLOBAL) persistent_global_config(s, &cfg);
+    if (mode == LPDEC_MODE_STREAMED) {
+        if (ncodes > 1 || code_of_frame)
+            return fail(LPDEC_EUNSUPPORTED, "the streamed form decodes one code per call");
+        streamed_config(s, half, &cfg);
+    }
+
+    WsGuard guard(c0->ws, stream);
+    Workspace &ws = c0->ws;
+
+    // per-launch code table and frame metadata
+    const DevCode *codes_dev = c0->d_dc;
+    FrameBatch fb{};
+    fb.nframes = nframes;
+    fb.llr = llr;
+    fb.x_out = x_out;
+    fb.iters_out = iters_out;
+    fb.flags_out = flags_out;
+    if (ncodes > 1 || code_of_frame) {
+        std::vector<DevCode> tbl(ncodes);
+        for (int c = 0; c < ncodes; ++c) tbl[c] = codes[c]->dc;
+        HIP_TRY(ws.codes.ensure(sizeof(DevCode) * ncodes));
+        HIP_TRY(hipMemcpyAsync(ws.codes.p, tbl.data(), sizeof(DevCode) * ncodes, hipMemcpyHostToDevice, stream));
+        codes_dev = static_cast<const DevCode *>(ws.codes.p);
+        const size_t bytes = (size_t)nframes * (sizeof(int32_t) + 2 * sizeof(int64_t));
+        HIP_TRY(ws.frame_meta.ensure(bytes));
+        char *base = static_cast<char *>(ws.frame_meta.p);
+        int64_t *d_loff = reinterpret_cast<int64_t *>(base);
+        int64_t *d_xoff = d_loff + nframes;
+        int32_t *d_cof = reinterpret_cast<int32_t *>(d_xoff + nframes);
+        HIP_TRY(hipMemcpyAsync(d_loff, llr_off, sizeof(int64_t) * nframes, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(d_xoff, x_off, sizeof(int64_t) * nframes, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(d_cof, code_of_frame, sizeof(int32_t) * nframes, hipMemcpyHostToDevice, stream));
+        fb.llr_off = d_loff;
+        fb.x_off = d_xoff;
+        fb.code_of_frame = d_cof;
+    }
+    IterParams ip{};
+    ip.mu_inv = 1.0f / p.mu;
+    ip.rho = p.rho;
+    ip.tol2 = p.tol * p.tol;
+    ip.max_iter = p.max_iter;
+    StateIO sio{};
+    if (state_flags & LPDEC_STATE_IN) {
+        sio.z_in = z_state;
+        sio.u_in = u_state;
+    }
+    if (state_flags & LPDEC_STATE_OUT) {
+        sio.z_out = z_state;
+        sio.u_out = u_state;
+    }
+    StreamArgs sa{};
+
+    if (cfg.form == Form::Resident || cfg.form == Form::PersistentGlobal) {
+        cfg.grid = occupancy_grid(cfg, nframes);
+        HIP_TRY(ws.queue.ensure(sizeof(int)));
+        fb.queue = static_cast<int *>(ws.queue.p);
+        HIP_TRY(launch_fill_i32(fb.queue, 0, 1, stream));
+        if (cfg.form == Form::PersistentGlobal) {
+            HIP_TRY(ws.gstate.ensure(2 * sizeof(float) * (size_t)cfg.grid * cfg.state_stride));
+            sa.z = ws.gstate.p;
+            sa.u = static_cast<float *>(ws.gstate.p) + (size_t)cfg.grid * cfg.state_stride;
+            if (!cfg.lds_slots) {
+                HIP_TRY(ws.gslots.ensure(sizeof(float) * (size_t)cfg.grid * cfg.slot_stride));
+                sa.gslots = static_cast<float *>(ws.gslots.p);
+            }
+        }
+        hipError_t e = launch_decode(cfg, codes_dev, fb, ip, sio, sa, stream);
+        if (e != hipSuccess) return fail(LPDEC_EDEVICE, "decode launch failed: %s", hipGetErrorString(e));
+    } else {
+        // streamed: state [frames][E_int] in HBM, one launch per iteration
+        const size_t esz = half ? 2 : 4;
+        const size_t per = (size_t)s.Eint_max;
+        HIP_TRY(ws.z.ensure(esz * per * nframes));
+        HIP_TRY(ws.u.ensure(esz * per * nframes));
+        HIP_TRY(ws.st.ensure(sizeof(StreamFrame) * nframes));
+        HIP_TRY(ws.active.ensure(sizeof(int) * 2));
+        if (!ws.host_active) HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&ws.host_active), 2 * sizeof(int)));
+        sa.z = ws.z.p;
+        sa.u = ws.u.p;
+        sa.st = static_cast<StreamFrame *>(ws.st.p);
+        sa.active_count = static_cast<int *>(ws.active.p);
+        cfg.grid = occupancy_grid(cfg, nframes);
+        if (!cfg.lds_slots) {
+            HIP_TRY(ws.gslots.ensure(sizeof(float) * (size_t)cfg.grid * cfg.slot_stride));
+            sa.gslots = static_cast<float *>(ws.gslots.p);
+        }
+        HIP_TRY(launch_stream_init(codes_dev, nframes, cfg, fb, sio, sa, ip, stream));
+        // Iterations are issued in blocks; after each block the number of frames
+        // still running is copied to pinned memory and checked one block later.
+        const int block = 16;
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+        int issued = 0, blk = 0;
+        lpdec_status rs = LPDEC_OK;
+        while (issued < p.max_iter) {
+            const int cnt = std::min(block, p.max_iter - issued);
+            for (int k = 0; k < cnt; ++k) {
+                hipError_t e = launch_fill_i32(sa.active_count, 0, 1, stream);
+                if (e == hipSuccess) e = launch_decode(cfg, codes_dev, fb, ip, sio, sa, stream);
+                if (e != hipSuccess) {
+                    rs = fail(LPDEC_EDEVICE, "streamed launch failed: %s", hipGetErrorString(e));
+                    break;
+                }
+            }
+            if (rs != LPDEC_OK) break;
+            issued += cnt;
+            const int slot = blk & 1;
+            hipError_t e = hipMemcpyAsync(ws.host_active + slot, sa.active_count, sizeof(int), hipMemcpyDeviceToHost,
+                                          stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[slot], stream);
+            if (e != hipSuccess) {
+                rs = fail(LPDEC_EDEVICE, "progress copy failed: %s", hipGetErrorString(e));
+                break;
+            }
+            if (blk > 0) {
+                const int prev = slot ^ 1;
+                e = hipEventSynchronize(ev[prev]);
+                if (e != hipSuccess) {
+                    rs = fail(LPDEC_EDEVICE, "progress wait failed: %s", hipGetErrorString(e));
+                    break;
+                }
+                if (ws.host_active[prev] == 0) break;
+            }
+            ++blk;
+        }
+        (void)hipEventSynchronize(ev[0]);
+        (void)hipEventSynchronize(ev[1]);
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        if (rs != LPDEC_OK) return rs;
+        if (sio.z_out) HIP_TRY(launch_stream_export(codes_dev, nframes, s.Eint_max, half, sio, sa, stream));
+    }
+    return LPDEC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+lpdec_params lpdec_default_params(void) {
+    lpdec_params p;
+    p.mu = 3.0f;
+    p.rho = 1.9f;
+    p.max_iter = 1000;
+    p.tol = 1e-5f;
+    p.storage = LPDEC_STORAGE_FP32;
+    p.mode = LPDEC_MODE_AUTO;
+    return p;
+}
+
+const char *lpdec_last_error(void) { return g_last_error.c_str(); }
+
+lpdec_status lpdec_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                               lpdec_code **out) {
+    if (!out) return fail(LPDEC_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    std::unique_ptr<lpdec_code> code(new (std::nothrow) lpdec_code());
+    if (!code) return fail(LPDEC_ENOMEM, "host allocation failed");
+    lpdec_status st = build_plan(m, n, nnz, row_ptr, col_idx, code.get());
+    if (st != LPDEC_OK) return st;
+    const lpdec_code *one = code.get();
+    code->resident_ok = resident_config(shape_of(&one, 1), &code->resident_cfg);
+    *out = code.release();
+    return LPDEC_OK;
+}
+
+void lpdec_code_destroy(lpdec_code *code) {
+    if (!code) return;
+    {
+        std::lock_guard<std::mutex> lk(code->ws.mu);
+        if (code->ws.last) (void)hipEventSynchronize(code->ws.last);
+    }
+    delete code;
+}
+
+lpdec_status lpdec_code_get_info(const lpdec_code *code, lpdec_code_info *info) {
+    if (!code || !info) return fail(LPDEC_EINVAL, "code and info must not be NULL");
+    info->m = code->dc.m;
+    info->n = code->dc.n;
+    info->nnz = code->dc.E;
+    info->min_check_degree = code->dc.dmin;
+    info->max_check_degree = code->dc.dmax;
+    info->resident_capable = code->resident_ok ? 1 : 0;
+    info->threads_per_frame = code->dc.waves * kWave;
+    return LPDEC_OK;
+}
+
+lpdec_status lpdec_decode(const lpdec_code *code, int32_t batch, const float *llr, const lpdec_params *p,
+                          float *x_out, int32_t *iters_out, uint8_t *flags_out, void *stream) {
+    if (!code) return fail(LPDEC_EINVAL, "code must not be NULL");
+    return decode_core(&code, 1, batch, nullptr, nullptr, nullptr, llr, p, x_out, iters_out, flags_out, nullptr,
+                       nullptr, 0, stream);
+}
+
+lpdec_status lpdec_decode_state(const lpdec_code *code, int32_t batch, const float *llr, const lpdec_params *p,
+                                float *x_out, int32_t *iters_out, uint8_t *flags_out, float *z_state,
+                                float *u_state, int32_t state_flags, void *stream) {
+    if (!code) return fail(LPDEC_EINVAL, "code must not be NULL");
+    if (state_flags & ~(LPDEC_STATE_IN | LPDEC_STATE_OUT)) return fail(LPDEC_EINVAL, "unknown state_flags bits");
+    return decode_core(&code, 1, batch, nullptr, nullptr, nullptr, llr, p, x_out, iters_out, flags_out, z_state,
+                       u_state, state_flags, stream);
+}
+
+lpdec_status lpdec_decode_multi(const lpdec_code *const *codes, int32_t ncodes, int32_t nframes,
+                                const int32_t *code_of_frame, const int64_t *llr_offset, const float *llr,
+                                int64_t llr_len, const lpdec_params *p, float *x_out, const int64_t *x_offset,
+                                int64_t x_len, int32_t *iters_out, uint8_t *flags_out, void *stream) {
+    if (!codes || ncodes < 1) return fail(LPDEC_EINVAL, "codes must hold >= 1 code");
+    for (int c = 0; c < ncodes; ++c)
+        if (!codes[c]) return fail(LPDEC_EINVAL, "codes[%d] is NULL", c);
+    if (nframes < 0) return fail(LPDEC_EINVAL, "nframes must be >= 0");
+    if (nframes == 0) return LPDEC_OK;
+    if (!code_of_frame || !llr_offset || !x_offset)
+        return fail(LPDEC_EINVAL, "code_of_frame, llr_offset and x_offset must not be NULL");
+    for (int f = 0; f < nframes; ++f) {
+        const int c = code_of_frame[f];
+        if (c < 0 || c >= ncodes) return fail(LPDEC_EINVAL, "frame %d: code index %d out of range", f, c);
+        const int64_t n = codes[c]->dc.n;
+        if (llr_offset[f] < 0 || llr_offset[f] + n > llr_len)
+            return fail(LPDEC_EINVAL, "frame %d: llr range [%lld, %lld) outside llr_len %lld", f,
+                        (long long)llr_offset[f], (long long)(llr_offset[f] + n), (long long)llr_len);
+        if (x_offset[f] < 0 || x_offset[f] + n > x_len)
+            return fail(LPDEC_EINVAL, "frame %d: x range outside x_len %lld", f, (long long)x_len);
+    }
+    lpdec_params pp = p ? *p : lpdec_default_params();
+    if (pp.mode == LPDEC_MODE_STREAMED || pp.storage == LPDEC_STORAGE_FP16)
+        return fail(LPDEC_EUNSUPPORTED, "multi-code decoding runs in one persistent launch (FP32)");
+    return decode_core(codes, ncodes, nframes, code_of_frame, llr_offset, x_offset, llr, &pp, x_out, iters_out,
+                       flags_out, nullptr, nullptr, 0, stream);
+}
+
+lpdec_status lpdec_project(int32_t d, int32_t count, const float *v, float *z, void *stream) {
+    if (d < 2 || d > LPDEC_MAX_CHECK_DEGREE)
+        return fail(LPDEC_EINVAL, "degree %d outside [2, %d]", d, LPDEC_MAX_CHECK_DEGREE);
+    if (count < 0) return fail(LPDEC_EINVAL, "count must be >= 0");
+    if (count == 0) return LPDEC_OK;
+    if (!v || !z) return fail(LPDEC_EINVAL, "v and z must not be NULL");
+    if (v == z) return fail(LPDEC_EINVAL, "z must not alias v");
+    hipError_t e = launch_project(d, count, v, z, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(LPDEC_EDEVICE, "projection launch failed: %s", hipGetErrorString(e));
+    return LPDEC_OK;
+}
+
+}  // extern "C"

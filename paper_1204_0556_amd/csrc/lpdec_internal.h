@@ -1,0 +1,119 @@
+// Internal structures shared by the host runtime (lpdec_host.cpp) and the HIP
+// kernels (lpdec_kernels.hip) of the same library.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lpdec {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kMaxThreads = 1024;  // workgroup limit
+constexpr int kMaxWaves = kMaxThreads / kWave;
+constexpr int kMaxD = 8;           // LPDEC_MAX_CHECK_DEGREE
+
+// Device view of one code (all pointers are device memory owned by the code).
+//
+// Checks are grouped by degree and cut into "chunks" of up to 64 checks of one
+// degree; one wavefront lane owns one check of a chunk.  A chunk's edge state is
+// stored lane-minor: edge k of lane l sits at chunk_off + k*64 + l, so a wave
+// touching edge k of its 64 checks reads 256 contiguous bytes.
+//
+// Variables are renumbered in order of decreasing degree; variable i's edges
+// occupy a contiguous "slot" range (its CSC block), in ascending CSR edge order.
+// Each edge knows its internal variable and slot.
+struct DevCode {
+    int m, n, E;          // checks, variables, nnz
+    int E_int;            // length of the lane-minor edge arrays (with padding)
+    int nchunks;          // chunks of <= 64 checks
+    int waves;            // wavefronts per workgroup for this code
+    int cpt;              // chunks per wave (chunk c belongs to wave c % waves)
+    int dmin, dmax;
+    int var_identity;     // internal variable order equals the original one
+    // Variables sorted by decreasing degree form nvc <= 8 classes: class c holds
+    // internal variables [vc_start[c], vc_start[c+1]) of degree vc_deg[c], whose
+    // slots start at vc_slot0[c].
+    int nvc;
+    int vc_start[9];
+    int vc_slot0[8];
+    int vc_deg[8];
+    float vc_inv[8];
+    const int *chunk_deg;     // [nchunks]
+    const int *chunk_off;     // [nchunks] offset into the lane-minor arrays
+    const int *chunk_cnt;     // [nchunks] checks in the chunk (<= 64)
+    const uint32_t *edge_meta;// [E_int] (slot << 16) | internal variable (0 on padding)
+    const int *edge_csr;      // [E_int] CSR edge id (-1 on padding)
+    const int *var_orig;      // [n] internal -> original variable index
+};
+
+// Frames of one launch.
+struct FrameBatch {
+    int nframes;
+    const int *code_of_frame;   // device [nframes] or nullptr (all code 0)
+    const int64_t *llr_off;     // device [nframes] or nullptr (f * n)
+    const float *llr;
+    float *x_out;
+    const int64_t *x_off;       // device [nframes] or nullptr (f * n)
+    int *iters_out;
+    uint8_t *flags_out;
+    int *queue;                 // device work counter (persistent kernels)
+};
+
+struct IterParams {
+    float mu_inv;   // 1 / mu
+    float rho;
+    float tol2;     // tol^2 (threshold = tol^2 * E)
+    int max_iter;
+};
+
+// Optional state input/output in CSR edge order ([frame][E]).
+struct StateIO {
+    const float *z_in, *u_in;
+    float *z_out, *u_out;
+};
+
+// Per-frame bookkeeping of the per-iteration (streamed) form.
+struct StreamFrame {
+    int iter;       // iterations completed
+    int done;       // 1 once converged / finished / invalid
+};
+
+struct StreamArgs {
+    void *z;                // [frames][E_int] fp32 or fp16
+    void *u;
+    StreamFrame *st;        // [frames]
+    int *active_count;      // device counter of frames still running after this launch
+    float *gslots;          // [workgroups][slot_stride] slot scratch when slots live in global memory
+};
+
+// Launchers (defined in lpdec_kernels.hip).  Return hipSuccess or the launch error.
+enum class Form { Resident, PersistentGlobal, Streamed };
+
+struct LaunchConfig {
+    Form form;
+    int cpt_tmpl;      // register-held chunks per wave: 0 (re-read), 2 or 4
+    int vpt_tmpl;      // register-held variables per thread (resident form): 4 or 8
+    int dclass;        // 0: degrees exactly 6; 1: degrees 2..8
+    bool lds_slots;    // slots in LDS (else global scratch)
+    bool half;         // fp16 state storage (streamed only)
+    int threads;       // workgroup size
+    int grid;          // workgroups
+    size_t lds_bytes;  // dynamic LDS
+    int lds_E;         // LDS slot array length (x follows it) when slots are in LDS
+    int slot_stride;   // per-workgroup stride of global slot scratch (floats)
+    int state_stride;  // per-workgroup stride of global state scratch (persistent-global form)
+};
+
+hipError_t launch_decode(const LaunchConfig &cfg, const DevCode *codes_dev, const FrameBatch &fb,
+                         const IterParams &ip, const StateIO &sio, const StreamArgs &sa,
+                         hipStream_t stream);
+hipError_t launch_stream_init(const DevCode *codes_dev, int nframes, const LaunchConfig &cfg,
+                              const FrameBatch &fb, const StateIO &sio, const StreamArgs &sa,
+                              const IterParams &ip, hipStream_t stream);
+hipError_t decode_occupancy(const LaunchConfig &cfg, int *blocks_per_cu);
+hipError_t launch_stream_export(const DevCode *codes_dev, int nframes, int E_int, bool half, const StateIO &sio,
+                                const StreamArgs &sa, hipStream_t stream);
+hipError_t launch_project(int d, int count, const float *v, float *z, hipStream_t stream);
+hipError_t launch_fill_i32(int *p, int value, int count, hipStream_t stream);
+
+}  // namespace lpdec

@@ -1,0 +1,771 @@
+// HIP kernels (gfx950) for ADMM LP decoding.
+//
+// Paper: Barman, Liu, Draper, Recht, "Decomposition Methods for Large Scale LP
+// Decoding" (arXiv 1204.0556).  One iteration of Algorithm 1 (Sec. 3.3), with
+// the over-relaxation of Sec. 5.2, is three phases over one frame, executed by
+// one workgroup:
+//   A  each check lane writes w_e = z_e - u_e (u = lambda/mu) into the slot of
+//      edge e; a variable's slots are contiguous (its CSC block)
+//   B  x_i = Pi_[0,1]( (sum_slots w - gamma_i/mu) / |N_v(i)| )          (Sec. 3.2)
+//   C  per check: v = rho x + (1 - rho) z + u, z' = Pi_PPd(v)  (Sec. 3.2, Alg. 2),
+//      u' = v - z', and the two residuals of the stopping rule (Alg. 1)
+// Phases are separated by workgroup barriers; slot and x exchanges go through
+// LDS (or, for codes too large for LDS, a per-workgroup global scratch).  Sums
+// use a fixed order, so a frame's result does not depend on what else runs.
+//
+// Forms (template flags):
+//   RES      the frame's z,u stay in registers across iterations (persistent)
+//   PERSIST  one launch decodes frames to completion, pulling frame indices
+//            from an atomic queue (per-frame early termination)
+//   neither  one launch = one iteration for every unfinished frame; z,u live in
+//            HBM between launches (FP32 or FP16 storage)
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "lpdec_internal.h"
+
+namespace lpdec {
+
+__device__ __forceinline__ float clamp01(float a) { return __builtin_amdgcn_fmed3f(a, 0.0f, 1.0f); }
+
+__device__ __forceinline__ bool finite_bits(float a) {
+    return (__float_as_uint(a) & 0x7f800000u) != 0x7f800000u;
+}
+
+// ---------------------------------------------------------------------------
+// Check-node operation: Euclidean projection onto PP_d (Sec. 4).
+//
+// With zhat = Pi_[0,1](v) and r the even floor of ||zhat||_1 (Lemma
+// const_parity), the projection is zhat when r = d or f_r^T zhat <= r (f_r =
+// +1 on the r+1 largest entries, -1 elsewhere; Alg. 2's early returns), and
+// otherwise z(beta) = Pi_[0,1](v - beta f_r) with f_r^T z(beta_opt) = r on
+// [0, beta_max] (Lemma optimality).  By the proposition of Sec. 4.4 only the
+// breakpoints E1 = {v_k - 1 : k <= r+1} and E2 = {-v_k : k >= r+2} matter, and
+// on [0, beta_opt] f_r^T z(beta) equals sum_k min(c_k, a_k - beta) with
+// (a_k, c_k) = (v_k, 1) on the top entries and (-v_k, 0) on the others: a
+// concave decreasing function, the minimum of the lines
+//     L_S(beta) = sum_{k in S} (a_k - beta) + sum_{k not in S} c_k ,  S != {} .
+// Its root is therefore the smallest root of those lines,
+//     beta_opt = min_S (1 + sum_{k in S} b_k) / |S| ,   b_k = a_k - c_k,
+// and for a given |S| = p the best S is the p smallest breakpoints.  In sorted
+// order the breakpoints s_k - 1 (k <= r) then -s_k (k > r) form a V-shaped
+// (bitonic) list, so one bitonic merge sorts them; beta_opt is then the least
+// prefix average.  Everything is branch-free after the early returns and uses
+// only static register indices.
+// ---------------------------------------------------------------------------
+#define LPD_CE(a, b)                                   \
+    {                                                  \
+        const float _p = s[a], _q = s[b];              \
+        s[a] = fmaxf(_p, _q);                          \
+        s[b] = fminf(_p, _q);                          \
+    }
+#include "sortnet.inc"
+
+template <int D>
+__device__ __forceinline__ void sort_desc(float *s) {
+    if constexpr (D == 2) { LPD_NET_2 }
+    else if constexpr (D == 3) { LPD_NET_3 }
+    else if constexpr (D == 4) { LPD_NET_4 }
+    else if constexpr (D == 5) { LPD_NET_5 }
+    else if constexpr (D == 6) { LPD_NET_6 }
+    else if constexpr (D == 7) { LPD_NET_7 }
+    else if constexpr (D == 8) { LPD_NET_8 }
+}
+#undef LPD_CE
+
+template <int P>
+__device__ __forceinline__ void bitonic_merge_asc(float *b) {
+#pragma unroll
+    for (int k = P / 2; k >= 1; k >>= 1) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            if ((i & k) == 0) {
+                const float p = b[i], q = b[i + k];
+                b[i] = fminf(p, q);
+                b[i + k] = fmaxf(p, q);
+            }
+        }
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void project_pp(const float *v, float *z) {
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        z[k] = clamp01(v[k]);
+        s += z[k];
+    }
+    const float rf = 2.0f * floorf(0.5f * s);  // constituent parity r
+    if (rf >= (float)D) return;                 // r = d
+    float sv[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) sv[k] = v[k];
+    sort_desc<D>(sv);
+    float g0 = 0.0f;  // f_r^T zhat, signs by sorted position
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const float c = clamp01(sv[k]);
+        g0 += ((float)k <= rf) ? c : -c;
+    }
+    if (g0 <= rf) return;  // zhat lies in PP_d
+    // t1 = v_(r+1), t2 = v_(r+2) (1-based order statistics); r is even
+    float t1 = sv[0];
+    float t2 = (D > 1) ? sv[1] : -INFINITY;
+#pragma unroll
+    for (int k = 2; k < D; k += 2) {
+        if (rf == (float)k) {
+            t1 = sv[k];
+            t2 = (k + 1 < D) ? sv[k + 1] : -INFINITY;
+        }
+    }
+    const bool all_top = (rf + 1.0f >= (float)D);
+    if (!all_top && !(t1 > t2)) return;  // beta_max = 0
+    const float beta_max = all_top ? t1 : 0.5f * (t1 - t2);
+    constexpr int P = (D <= 2) ? 2 : ((D <= 4) ? 4 : 8);
+    float bp[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k)
+        bp[k] = (k < D) ? (((float)k <= rf) ? sv[k] - 1.0f : -sv[k]) : INFINITY;
+    bitonic_merge_asc<P>(bp);
+    float acc = 1.0f, beta = INFINITY;
+#pragma unroll
+    for (int p = 1; p <= D; ++p) {
+        acc += bp[p - 1];
+        beta = fminf(beta, acc * (1.0f / (float)p));
+    }
+    beta = fminf(fmaxf(beta, 0.0f), beta_max);
+#pragma unroll
+    for (int k = 0; k < D; ++k) z[k] = clamp01(v[k] - ((v[k] >= t1) ? beta : -beta));
+}
+
+// ---------------------------------------------------------------------------
+// Standalone check-node kernel (lpdec_project): one lane per vector.
+template <int D>
+__global__ void __launch_bounds__(256) k_project(int count, const float *__restrict__ v,
+                                                 float *__restrict__ z) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    float a[D], b[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) a[k] = v[(size_t)t * D + k];
+    project_pp<D>(a, b);
+#pragma unroll
+    for (int k = 0; k < D; ++k) z[(size_t)t * D + k] = b[k];
+}
+
+hipError_t launch_project(int d, int count, const float *v, float *z, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    const dim3 block(256), grid((count + 255) / 256);
+    switch (d) {
+        case 2: hipLaunchKernelGGL(k_project<2>, grid, block, 0, stream, count, v, z); break;
+        case 3: hipLaunchKernelGGL(k_project<3>, grid, block, 0, stream, count, v, z); break;
+        case 4: hipLaunchKernelGGL(k_project<4>, grid, block, 0, stream, count, v, z); break;
+        case 5: hipLaunchKernelGGL(k_project<5>, grid, block, 0, stream, count, v, z); break;
+        case 6: hipLaunchKernelGGL(k_project<6>, grid, block, 0, stream, count, v, z); break;
+        case 7: hipLaunchKernelGGL(k_project<7>, grid, block, 0, stream, count, v, z); break;
+        case 8: hipLaunchKernelGGL(k_project<8>, grid, block, 0, stream, count, v, z); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int *p, int value, int count) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) p[t] = value;
+}
+
+hipError_t launch_fill_i32(int *p, int value, int count, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((count + 255) / 256), dim3(256), 0, stream, p, value, count);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup helpers.
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+
+template <int DMIN, int DMAX, typename F>
+__device__ __forceinline__ void dispatch_degree(int d, F &&f) {
+    if constexpr (DMIN == DMAX) {
+        f(std::integral_constant<int, DMIN>{});
+    } else {
+        if (d == DMIN) f(std::integral_constant<int, DMIN>{});
+        else dispatch_degree<DMIN + 1, DMAX>(d, f);
+    }
+}
+
+// x-update of one variable from its slots (Sec. 3.2).  Variables are numbered
+// by decreasing degree, so the code describes them by at most 8 degree classes.
+struct VarLoc {
+    int slot0, deg;
+    float inv;
+};
+
+__device__ __forceinline__ VarLoc var_loc(const DevCode &C, int i) {
+    int c = 0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k)
+        if (k < C.nvc && i >= C.vc_start[k]) c = k;
+    VarLoc L;
+    L.deg = C.vc_deg[c];
+    L.slot0 = C.vc_slot0[c] + (i - C.vc_start[c]) * L.deg;
+    L.inv = C.vc_inv[c];
+    return L;
+}
+
+__device__ __forceinline__ float x_update(const float *slots, const VarLoc &L, float gmu) {
+    float s = 0.0f;
+    for (int p = 0; p < L.deg; ++p) s += slots[L.slot0 + p];
+    return clamp01((s - gmu) * L.inv);
+}
+
+// one check update of degree D on registers z,u (length DMAX arrays)
+template <int D>
+__device__ __forceinline__ void check_update(float *z, float *u, const uint32_t *meta, const float *xs,
+                                             float rho, float &rp, float &rd) {
+    float v[D], zn[D], xv[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        xv[k] = xs[meta[k] & 0xffffu];
+        v[k] = fmaf(rho, xv[k] - z[k], z[k]) + u[k];  // q + u with q = rho x + (1-rho) z
+    }
+    project_pp<D>(v, zn);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const float dx = xv[k] - zn[k];
+        const float dz = zn[k] - z[k];
+        rp = fmaf(dx, dx, rp);
+        rd = fmaf(dz, dz, rd);
+        u[k] = v[k] - zn[k];
+        z[k] = zn[k];
+    }
+}
+
+template <bool HALF>
+__device__ __forceinline__ float ld_state(const void *p, size_t i) {
+    if constexpr (HALF) return __half2float(static_cast<const __half *>(p)[i]);
+    else return static_cast<const float *>(p)[i];
+}
+template <bool HALF>
+__device__ __forceinline__ void st_state(void *p, size_t i, float a) {
+    if constexpr (HALF) static_cast<__half *>(p)[i] = __float2half_rn(a);
+    else static_cast<float *>(p)[i] = a;
+}
+
+// ---------------------------------------------------------------------------
+// The decoder kernel.
+//
+// Check side: wave w owns chunks c = w + k*C.waves (k < C.cpt); lane l owns
+// check l of each of them.  CPT > 0 keeps those chunks' z,u (and packed edge
+// metadata) in registers; CPT == 0 walks the chunks and re-reads state.
+// Variable side: thread t owns internal variables t, t + NT, ...
+template <int DMIN, int DMAX, int CPT, int VPT, bool RES, bool PERSIST, bool LDS_SLOTS, bool HALF, int MAXT>
+__global__ void __launch_bounds__(MAXT)
+k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateIO sio, StreamArgs sa,
+         int lds_E, int slot_stride, int state_stride) {
+    static_assert(!RES || (CPT > 0 && PERSIST && LDS_SLOTS), "register-resident form needs CPT>0");
+    extern __shared__ float lds[];
+    __shared__ float s_red[2][2][kMaxWaves];
+    __shared__ int s_frame;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid >> 6;
+    const int NT = blockDim.x;
+    const int NW = NT >> 6;
+
+    float *slots = LDS_SLOTS ? lds : (sa.gslots + (size_t)blockIdx.x * slot_stride);
+    float *xs = LDS_SLOTS ? (lds + lds_E) : lds;
+
+    constexpr int NC = CPT > 0 ? CPT : 1;
+    float z[NC][DMAX], u[NC][DMAX];
+    uint32_t meta[NC][DMAX];
+    int cdeg[NC], coff[NC];
+    bool cval[NC];
+    float vg[VPT > 0 ? VPT : 1];
+    int cur_code = -1;
+
+    int next_f = blockIdx.x;
+    for (;;) {
+        int f;
+        if constexpr (PERSIST) {
+            if (tid == 0) s_frame = atomicAdd(fb.queue, 1);
+            __syncthreads();
+            f = s_frame;
+            __syncthreads();
+        } else {
+            f = next_f;
+            next_f += gridDim.x;
+        }
+        if (f >= fb.nframes) break;
+
+        const int ci = fb.code_of_frame ? fb.code_of_frame[f] : 0;
+        const DevCode &C = codes[ci];
+        const int64_t loff = fb.llr_off ? fb.llr_off[f] : (int64_t)f * C.n;
+        const float *gam = fb.llr + loff;
+        const float thr = ip.tol2 * (float)C.E;
+
+        int iter0 = 0;
+        if constexpr (!PERSIST) {
+            const StreamFrame st = sa.st[f];
+            if (st.done) continue;
+            iter0 = st.iter;
+        }
+
+        // -- per-code register metadata -------------------------------------
+        if constexpr (CPT > 0) {
+            if (ci != cur_code) {
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    const int c = wave + k * C.waves;
+                    const bool has = (wave < C.waves) && (k < C.cpt) && (c < C.nchunks);
+                    cdeg[k] = has ? __builtin_amdgcn_readfirstlane(C.chunk_deg[c]) : 0;
+                    coff[k] = has ? __builtin_amdgcn_readfirstlane(C.chunk_off[c]) : 0;
+                    cval[k] = has && (lane < C.chunk_cnt[c]);
+#pragma unroll
+                    for (int e = 0; e < DMAX; ++e)
+                        meta[k][e] = (cval[k] && e < cdeg[k]) ? C.edge_meta[coff[k] + e * kWave + lane] : 0u;
+                }
+                cur_code = ci;
+            }
+        }
+
+        // -- frame set-up: gamma/mu, invalid-input check ----------------------
+        bool bad = false;
+        if constexpr (VPT > 0) {
+#pragma unroll
+            for (int t = 0; t < VPT; ++t) {
+                const int i = tid + t * NT;
+                float g = 0.0f;
+                if (i < C.n) {
+                    g = gam[C.var_identity ? i : C.var_orig[i]];
+                    bad |= !finite_bits(g);
+                }
+                vg[t] = g * ip.mu_inv;
+            }
+        } else if constexpr (PERSIST) {
+            for (int i = tid; i < C.n; i += NT) bad |= !finite_bits(gam[i]);
+        }
+        if constexpr (PERSIST) {
+            if (__syncthreads_or(bad)) {
+                for (int i = tid; i < C.n; i += NT)
+                    fb.x_out[(fb.x_off ? fb.x_off[f] : (int64_t)f * C.n) + i] = 0.5f;
+                if (tid == 0) {
+                    fb.iters_out[f] = 0;
+                    fb.flags_out[f] = 0x80;
+                }
+                __syncthreads();
+                continue;
+            }
+        }
+
+        // state location in global memory (non-resident forms)
+        void *gz = nullptr;
+        void *gu = nullptr;
+        if constexpr (!RES) {
+            const size_t base = PERSIST ? (size_t)blockIdx.x * state_stride : (size_t)f * C.E_int;
+            gz = HALF ? (void *)(static_cast<__half *>(sa.z) + base) : (void *)(static_cast<float *>(sa.z) + base);
+            gu = HALF ? (void *)(static_cast<__half *>(sa.u) + base) : (void *)(static_cast<float *>(sa.u) + base);
+        }
+
+        // -- initial state (PERSIST forms; the streamed form is initialised by
+        //    its own kernel) -----------------------------------------------------
+        if constexpr (PERSIST) {
+            const size_t sbase = (size_t)f * C.E;
+            if constexpr (RES) {
+#pragma unroll
+                for (int k = 0; k < CPT; ++k)
+#pragma unroll
+                    for (int e = 0; e < DMAX; ++e) {
+                        float z0 = 0.0f, u0 = 0.0f;
+                        if (sio.z_in && cval[k] && e < cdeg[k]) {
+                            const int ce = C.edge_csr[coff[k] + e * kWave + lane];
+                            z0 = sio.z_in[sbase + ce];
+                            u0 = sio.u_in[sbase + ce];
+                        }
+                        z[k][e] = z0;
+                        u[k][e] = u0;
+                    }
+            } else {
+                for (int c = wave; c < C.nchunks && wave < C.waves; c += C.waves) {
+                    const int d = C.chunk_deg[c], off = C.chunk_off[c];
+                    const bool lv = lane < C.chunk_cnt[c];
+                    for (int e = 0; e < d; ++e) {
+                        const int p = off + e * kWave + lane;
+                        float z0 = 0.0f, u0 = 0.0f;
+                        if (sio.z_in && lv) {
+                            const int ce = C.edge_csr[p];
+                            z0 = sio.z_in[sbase + ce];
+                            u0 = sio.u_in[sbase + ce];
+                        }
+                        st_state<HALF>(gz, p, z0);
+                        st_state<HALF>(gu, p, u0);
+                    }
+                }
+            }
+        }
+
+        // -- phases ---------------------------------------------------------
+        auto phase_a = [&]() {
+            if constexpr (CPT > 0) {
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    if constexpr (!RES) {
+#pragma unroll
+                        for (int e = 0; e < DMAX; ++e) {
+                            if (cval[k] && e < cdeg[k]) {
+                                const size_t p = coff[k] + e * kWave + lane;
+                                z[k][e] = ld_state<HALF>(gz, p);
+                                u[k][e] = ld_state<HALF>(gu, p);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int e = 0; e < DMAX; ++e)
+                        if (cval[k] && e < cdeg[k]) slots[meta[k][e] >> 16] = z[k][e] - u[k][e];
+                }
+            } else {
+                for (int c = wave; c < C.nchunks && wave < C.waves; c += C.waves) {
+                    const int d = C.chunk_deg[c], off = C.chunk_off[c];
+                    if (lane < C.chunk_cnt[c]) {
+                        for (int e = 0; e < d; ++e) {
+                            const size_t p = off + e * kWave + lane;
+                            slots[C.edge_meta[p] >> 16] = ld_state<HALF>(gz, p) - ld_state<HALF>(gu, p);
+                        }
+                    }
+                }
+            }
+        };
+
+        auto phase_b = [&]() {
+            if constexpr (VPT > 0) {
+#pragma unroll
+                for (int t = 0; t < VPT; ++t) {
+                    const int i = tid + t * NT;
+                    if (i < C.n) xs[i] = x_update(slots, var_loc(C, i), vg[t]);
+                }
+            } else {
+                for (int i = tid; i < C.n; i += NT) {
+                    const float g = gam[C.var_identity ? i : C.var_orig[i]] * ip.mu_inv;
+                    xs[i] = x_update(slots, var_loc(C, i), g);
+                }
+            }
+        };
+
+        auto phase_c = [&](float &rp, float &rd) {
+            if constexpr (CPT > 0) {
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    if (cdeg[k] == 0) continue;  // wave-uniform
+                    if (cval[k]) {
+                        dispatch_degree<DMIN, DMAX>(cdeg[k], [&](auto dc) {
+                            constexpr int D = decltype(dc)::value;
+                            check_update<D>(z[k], u[k], meta[k], xs, ip.rho, rp, rd);
+                        });
+                    }
+                    if constexpr (!RES) {
+#pragma unroll
+                        for (int e = 0; e < DMAX; ++e) {
+                            if (cval[k] && e < cdeg[k]) {
+                                const size_t p = coff[k] + e * kWave + lane;
+                                st_state<HALF>(gz, p, z[k][e]);
+                                st_state<HALF>(gu, p, u[k][e]);
+                            }
+                        }
+                    }
+                }
+            } else {
+                for (int c = wave; c < C.nchunks && wave < C.waves; c += C.waves) {
+                    const int d = __builtin_amdgcn_readfirstlane(C.chunk_deg[c]);
+                    const int off = C.chunk_off[c];
+                    if (lane < C.chunk_cnt[c]) {
+                        dispatch_degree<DMIN, DMAX>(d, [&](auto dc) {
+                            constexpr int D = decltype(dc)::value;
+                            float zz[D], uu[D];
+                            uint32_t mm[D];
+#pragma unroll
+                            for (int e = 0; e < D; ++e) {
+                                const size_t p = off + e * kWave + lane;
+                                zz[e] = ld_state<HALF>(gz, p);
+                                uu[e] = ld_state<HALF>(gu, p);
+                                mm[e] = C.edge_meta[p];
+                            }
+                            check_update<D>(zz, uu, mm, xs, ip.rho, rp, rd);
+#pragma unroll
+                            for (int e = 0; e < D; ++e) {
+                                const size_t p = off + e * kWave + lane;
+                                st_state<HALF>(gz, p, zz[e]);
+                                st_state<HALF>(gu, p, uu[e]);
+                            }
+                        });
+                    }
+                }
+            }
+        };
+
+        auto publish = [&](int buf, float rp, float rd) {
+            rp = wave_sum(rp);
+            rd = wave_sum(rd);
+            if (lane == 0) {
+                s_red[buf][0][wave] = rp;
+                s_red[buf][1][wave] = rd;
+            }
+        };
+        auto converged = [&](int buf) -> bool {  // identical result in every wave
+            const float a = lane < NW ? s_red[buf][0][lane] : 0.0f;
+            const float b = lane < NW ? s_red[buf][1][lane] : 0.0f;
+            return wave_sum(a) < thr && wave_sum(b) < thr;
+        };
+
+        int iters;
+        bool conv = false;
+        if constexpr (PERSIST) {
+            int it = 1;
+            for (;; ++it) {
+                phase_a();
+                __syncthreads();
+                if (it > 1) {
+                    if (converged((it - 1) & 1)) { conv = true; break; }
+                    if (it > ip.max_iter) break;
+                }
+                phase_b();
+                __syncthreads();
+                float rp = 0.0f, rd = 0.0f;
+                phase_c(rp, rd);
+                publish(it & 1, rp, rd);
+            }
+            iters = conv ? it - 1 : ip.max_iter;
+        } else {
+            const int it = iter0 + 1;
+            phase_a();
+            __syncthreads();
+            phase_b();
+            __syncthreads();
+            float rp = 0.0f, rd = 0.0f;
+            phase_c(rp, rd);
+            publish(0, rp, rd);
+            __syncthreads();
+            conv = converged(0);
+            iters = it;
+            const bool fin = conv || it >= ip.max_iter;
+            if (tid == 0) {
+                sa.st[f].iter = it;
+                if (fin) sa.st[f].done = 1;
+                else atomicAdd(sa.active_count, 1);
+            }
+            if (!fin) {
+                __syncthreads();  // LDS reuse by the next frame of this workgroup
+                continue;
+            }
+        }
+
+        // -- epilogue: x, iteration count and certificate flags (x in LDS) ---------
+        const int64_t xoff = fb.x_off ? fb.x_off[f] : (int64_t)f * C.n;
+        float frac = 0.0f;
+        for (int i = tid; i < C.n; i += NT) {
+            const float x = xs[i];
+            fb.x_out[xoff + (C.var_identity ? i : C.var_orig[i])] = x;
+            frac = fmaxf(frac, fminf(x, 1.0f - x));
+        }
+        bool odd = false;
+        for (int c = wave; c < C.nchunks && wave < C.waves; c += C.waves) {
+            const int d = C.chunk_deg[c], off = C.chunk_off[c];
+            if (lane < C.chunk_cnt[c]) {
+                bool par = false;
+                for (int e = 0; e < d; ++e) par ^= (xs[C.edge_meta[off + e * kWave + lane] & 0xffffu] >= 0.5f);
+                odd |= par;
+            }
+        }
+        const bool nonint = (double)frac > 1e-3;
+        const int any_odd = __syncthreads_or(odd);
+        const int any_nonint = __syncthreads_or(nonint);
+        if (tid == 0) {
+            uint8_t fl = conv ? 0x01 : 0x00;
+            if (!any_nonint) fl |= 0x02;
+            if (!any_odd) fl |= 0x04;
+            if ((fl & 0x07) == 0x07) fl |= 0x08;
+            fb.iters_out[f] = iters;
+            fb.flags_out[f] = fl;
+        }
+        // state export (CSR edge order)
+        if (sio.z_out) {
+            const size_t sbase = (size_t)f * C.E;
+            if constexpr (RES) {
+#pragma unroll
+                for (int k = 0; k < CPT; ++k)
+#pragma unroll
+                    for (int e = 0; e < DMAX; ++e)
+                        if (cval[k] && e < cdeg[k]) {
+                            const int ce = C.edge_csr[coff[k] + e * kWave + lane];
+                            sio.z_out[sbase + ce] = z[k][e];
+                            sio.u_out[sbase + ce] = u[k][e];
+                        }
+            } else {
+                for (int c = wave; c < C.nchunks && wave < C.waves; c += C.waves) {
+                    const int d = C.chunk_deg[c], off = C.chunk_off[c];
+                    if (lane < C.chunk_cnt[c]) {
+                        for (int e = 0; e < d; ++e) {
+                            const size_t p = off + e * kWave + lane;
+                            const int ce = C.edge_csr[p];
+                            sio.z_out[sbase + ce] = ld_state<HALF>(gz, p);
+                            sio.u_out[sbase + ce] = ld_state<HALF>(gu, p);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Streamed form set-up: zero (or load) each frame's state, flag invalid frames.
+template <bool HALF>
+__global__ void __launch_bounds__(256)
+k_stream_init(const DevCode *__restrict__ codes, FrameBatch fb, StateIO sio, StreamArgs sa) {
+    const int f = blockIdx.x;
+    if (f >= fb.nframes) return;
+    const int ci = fb.code_of_frame ? fb.code_of_frame[f] : 0;
+    const DevCode &C = codes[ci];
+    const int64_t loff = fb.llr_off ? fb.llr_off[f] : (int64_t)f * C.n;
+    bool bad = false;
+    for (int i = threadIdx.x; i < C.n; i += blockDim.x) bad |= !finite_bits(fb.llr[loff + i]);
+    const int any_bad = __syncthreads_or(bad);
+    const size_t base = (size_t)f * C.E_int;
+    for (int p = threadIdx.x; p < C.E_int; p += blockDim.x) {
+        float z0 = 0.0f, u0 = 0.0f;
+        const int ce = C.edge_csr[p];
+        if (sio.z_in && ce >= 0) {
+            z0 = sio.z_in[(size_t)f * C.E + ce];
+            u0 = sio.u_in[(size_t)f * C.E + ce];
+        }
+        st_state<HALF>(sa.z, base + p, z0);
+        st_state<HALF>(sa.u, base + p, u0);
+    }
+    if (any_bad) {
+        const int64_t xoff = fb.x_off ? fb.x_off[f] : (int64_t)f * C.n;
+        for (int i = threadIdx.x; i < C.n; i += blockDim.x) fb.x_out[xoff + i] = 0.5f;
+    }
+    if (threadIdx.x == 0) {
+        sa.st[f].iter = 0;
+        sa.st[f].done = any_bad ? 1 : 0;
+        if (any_bad) {
+            fb.iters_out[f] = 0;
+            fb.flags_out[f] = 0x80;
+        }
+    }
+}
+
+hipError_t launch_stream_init(const DevCode *codes_dev, int nframes, const LaunchConfig &cfg,
+                              const FrameBatch &fb, const StateIO &sio, const StreamArgs &sa,
+                              const IterParams &, hipStream_t stream) {
+    if (nframes <= 0) return hipSuccess;
+    if (cfg.half)
+        hipLaunchKernelGGL(k_stream_init<true>, dim3(nframes), dim3(256), 0, stream, codes_dev, fb, sio, sa);
+    else
+        hipLaunchKernelGGL(k_stream_init<false>, dim3(nframes), dim3(256), 0, stream, codes_dev, fb, sio, sa);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Instantiation table.
+
+template <int DMIN, int DMAX, int CPT, int VPT, bool RES, bool PERSIST, bool LDS, bool HALF, int MAXT = kMaxThreads>
+static hipError_t go(const LaunchConfig &cfg, const DevCode *codes, const FrameBatch &fb, const IterParams &ip,
+                     const StateIO &sio, const StreamArgs &sa, hipStream_t stream, int *occ) {
+    if (cfg.threads > MAXT) return hipErrorInvalidConfiguration;
+    auto kern = k_decode<DMIN, DMAX, CPT, VPT, RES, PERSIST, LDS, HALF, MAXT>;
+    if (cfg.lds_bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg.lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    if (occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kern, cfg.threads, cfg.lds_bytes);
+    hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(cfg.threads), cfg.lds_bytes, stream, codes, fb, ip, sio, sa,
+                       cfg.lds_E, cfg.slot_stride, cfg.state_stride);
+    return hipGetLastError();
+}
+
+template <int DMIN, int DMAX>
+static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const FrameBatch &fb,
+                           const IterParams &ip, const StateIO &sio, const StreamArgs &sa, hipStream_t stream,
+                           int *occ) {
+#define LPD_GO(...) return go<DMIN, DMAX, __VA_ARGS__>(cfg, codes, fb, ip, sio, sa, stream, occ)
+    switch (cfg.form) {
+        case Form::Resident:
+            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4) LPD_GO(2, 4, true, true, true, false, 768);
+            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8) LPD_GO(2, 8, true, true, true, false, 768);
+            if (cfg.cpt_tmpl == 4 && cfg.vpt_tmpl == 8) LPD_GO(4, 8, true, true, true, false, 512);
+            break;
+        case Form::PersistentGlobal:
+            if (cfg.lds_slots) {
+                if (cfg.cpt_tmpl == 2) LPD_GO(2, 0, false, true, true, false);
+                if (cfg.cpt_tmpl == 0) LPD_GO(0, 0, false, true, true, false);
+            } else {
+                if (cfg.cpt_tmpl == 0) LPD_GO(0, 0, false, true, false, false);
+            }
+            break;
+        case Form::Streamed:
+            if (cfg.lds_slots) {
+                if (cfg.cpt_tmpl == 2 && !cfg.half) LPD_GO(2, 0, false, false, true, false);
+                if (cfg.cpt_tmpl == 2 && cfg.half) LPD_GO(2, 0, false, false, true, true);
+                if (cfg.cpt_tmpl == 0 && !cfg.half) LPD_GO(0, 0, false, false, true, false);
+                if (cfg.cpt_tmpl == 0 && cfg.half) LPD_GO(0, 0, false, false, true, true);
+            } else {
+                if (!cfg.half) LPD_GO(0, 0, false, false, false, false);
+                LPD_GO(0, 0, false, false, false, true);
+            }
+            break;
+    }
+#undef LPD_GO
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_decode(const LaunchConfig &cfg, const DevCode *codes_dev, const FrameBatch &fb,
+                         const IterParams &ip, const StateIO &sio, const StreamArgs &sa, hipStream_t stream) {
+    if (cfg.dclass == 0) return go_range<6, 6>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
+    return go_range<2, 8>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
+}
+
+hipError_t decode_occupancy(const LaunchConfig &cfg, int *blocks_per_cu) {
+    FrameBatch fb{};
+    IterParams ip{};
+    StateIO sio{};
+    StreamArgs sa{};
+    *blocks_per_cu = 0;
+    if (cfg.dclass == 0) return go_range<6, 6>(cfg, nullptr, fb, ip, sio, sa, nullptr, blocks_per_cu);
+    return go_range<2, 8>(cfg, nullptr, fb, ip, sio, sa, nullptr, blocks_per_cu);
+}
+
+// Streamed form: copy the final lane-minor state back to CSR edge order.
+template <bool HALF>
+__global__ void __launch_bounds__(256)
+k_stream_export(const DevCode *__restrict__ codes, int nframes, StateIO sio, StreamArgs sa) {
+    const int f = blockIdx.y;
+    const DevCode &C = codes[0];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nframes || p >= C.E_int) return;
+    const int ce = C.edge_csr[p];
+    if (ce < 0) return;
+    const size_t src = (size_t)f * C.E_int + p, dst = (size_t)f * C.E + ce;
+    sio.z_out[dst] = ld_state<HALF>(sa.z, src);
+    sio.u_out[dst] = ld_state<HALF>(sa.u, src);
+}
+
+hipError_t launch_stream_export(const DevCode *codes_dev, int nframes, int E_int, bool half, const StateIO &sio,
+                                const StreamArgs &sa, hipStream_t stream) {
+    if (nframes <= 0) return hipSuccess;
+    const dim3 grid((E_int + 255) / 256, nframes);
+    if (half) hipLaunchKernelGGL(k_stream_export<true>, grid, dim3(256), 0, stream, codes_dev, nframes, sio, sa);
+    else hipLaunchKernelGGL(k_stream_export<false>, grid, dim3(256), 0, stream, codes_dev, nframes, sio, sa);
+    return hipGetLastError();
+}
+
+}  // namespace lpdec

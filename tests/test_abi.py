@@ -1,0 +1,130 @@
+"""The C ABI: exported symbols and host-side error conventions (no GPU needed).
+
+These calls are all rejected on the host before any device work, so they run
+in the CPU suite; each must return the documented status and leave a message.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lpdec.h")
+LIB = os.path.join(ROOT, "paper_1204_0556_amd", "liblpdec.so")
+
+EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED = -1, -2, -3, -4
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lpdec_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("liblpdec.so is not built (run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB)
+    L.lpdec_last_error.restype = ctypes.c_char_p
+    return L
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for must in ("lpdec_code_create", "lpdec_code_destroy", "lpdec_decode", "lpdec_decode_state",
+                 "lpdec_decode_multi", "lpdec_project", "lpdec_last_error", "lpdec_default_params",
+                 "lpdec_code_get_info"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    for name in declared_functions():
+        assert re.search(rf"\bT {name}\b", out), name
+
+
+def _create(lib, m, n, row_ptr, col_idx):
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    ci = np.ascontiguousarray(col_idx, np.int32)
+    h = ctypes.c_void_p()
+    st = lib.lpdec_code_create(ctypes.c_int32(m), ctypes.c_int32(n), ctypes.c_int64(ci.size),
+                               rp.ctypes.data_as(ctypes.c_void_p), ci.ctypes.data_as(ctypes.c_void_p),
+                               ctypes.byref(h))
+    return st, h, lib.lpdec_last_error().decode()
+
+
+@pytest.mark.parametrize("case,m,n,rp,ci,status,msg", [
+    ("empty column", 2, 4, [0, 2, 4], [0, 1, 0, 1], EINVAL, "column 2"),
+    ("degree one row", 2, 3, [0, 1, 3], [0, 1, 2], EINVAL, "degree 1"),
+    ("duplicate index", 1, 3, [0, 3], [0, 0, 1], EINVAL, "strictly increasing"),
+    ("unsorted row", 1, 3, [0, 3], [2, 0, 1], EINVAL, "strictly increasing"),
+    ("index out of range", 1, 3, [0, 3], [0, 1, 3], EINVAL, "out of range"),
+    ("bad row_ptr end", 1, 3, [0, 2], [0, 1, 2], EINVAL, "nnz"),
+    ("degree above max", 1, 9, [0, 9], list(range(9)), EUNSUPPORTED, "degree 9"),
+    ("no rows", 0, 3, [0], [0], EINVAL, "m and n"),
+])
+def test_code_create_rejects(lib, case, m, n, rp, ci, status, msg):
+    st, h, err = _create(lib, m, n, rp, ci)
+    assert st == status, (case, st, err)
+    assert h.value is None
+    assert msg in err, (case, err)
+
+
+def test_null_arguments(lib):
+    lib.lpdec_decode.argtypes = [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 6
+    assert lib.lpdec_decode(None, 1, None, None, None, None, None, None) == EINVAL
+    assert "code" in lib.lpdec_last_error().decode()
+    lib.lpdec_code_destroy(None)  # NULL-safe
+
+
+def test_project_argument_checks(lib):
+    lib.lpdec_project.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.lpdec_project(9, 4, None, None, None) == EINVAL
+    assert lib.lpdec_project(1, 4, None, None, None) == EINVAL
+    assert lib.lpdec_project(6, -1, None, None, None) == EINVAL
+    assert lib.lpdec_project(6, 0, None, None, None) == 0  # empty batch is a no-op
+    assert lib.lpdec_project(6, 4, None, None, None) == EINVAL
+
+
+def test_multi_argument_checks(lib):
+    lib.lpdec_decode_multi.restype = ctypes.c_int
+    assert lib.lpdec_decode_multi(None, 0, 1, None, None, None, ctypes.c_int64(0), None, None, None,
+                                  ctypes.c_int64(0), None, None, None) == EINVAL
+
+
+def test_default_params(lib):
+    class P(ctypes.Structure):
+        _fields_ = [("mu", ctypes.c_float), ("rho", ctypes.c_float), ("max_iter", ctypes.c_int32),
+                    ("tol", ctypes.c_float), ("storage", ctypes.c_int32), ("mode", ctypes.c_int32)]
+    lib.lpdec_default_params.restype = P
+    p = lib.lpdec_default_params()
+    # Sec. 5.1: eps = 1e-5, mu = 3, t_max = 1000, rho = 1.9
+    assert (p.mu, p.max_iter, p.storage, p.mode) == (3.0, 1000, 0, 0)
+    assert abs(p.rho - 1.9) < 1e-6 and abs(p.tol - 1e-5) < 1e-12
+
+
+def test_sorting_networks_sort_every_binary_input(tmp_path):
+    """The kernels' compare-exchange networks (0-1 principle, all 2^d inputs)."""
+    inc = os.path.join(ROOT, "paper_1204_0556_amd", "csrc", "sortnet.inc")
+    src = tmp_path / "net.cpp"
+    src.write_text(f'''
+#include <cstdio>
+#define LPD_CE(a,b) {{ int p=s[a], q=s[b]; s[a]=p>q?p:q; s[b]=p>q?q:p; }}
+#include "{inc}"
+template <int D> int check(void (*f)(int*)) {{
+  for (int m = 0; m < (1 << D); ++m) {{ int s[8]; for (int k = 0; k < D; ++k) s[k] = (m >> k) & 1; f(s);
+    for (int k = 1; k < D; ++k) if (s[k-1] < s[k]) return 0; }}
+  return 1; }}
+void n2(int*s){{LPD_NET_2}} void n3(int*s){{LPD_NET_3}} void n4(int*s){{LPD_NET_4}} void n5(int*s){{LPD_NET_5}}
+void n6(int*s){{LPD_NET_6}} void n7(int*s){{LPD_NET_7}} void n8(int*s){{LPD_NET_8}}
+int main(){{ return !(check<2>(n2)&&check<3>(n3)&&check<4>(n4)&&check<5>(n5)&&check<6>(n6)&&check<7>(n7)&&check<8>(n8)); }}
+''')
+    exe = tmp_path / "net"
+    subprocess.check_call(["g++", "-O1", "-o", str(exe), str(src)])
+    assert subprocess.call([str(exe)]) == 0

@@ -1,0 +1,188 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances
+* Projection: both sides project the same FP32 input; the kernel works in FP32.
+  Its beta is a prefix average of <= 8 breakpoints of magnitude <= 1 + |v|, so
+  the error is a few FP32 ulps of (1 + max|v|): 2e-6 (1 + max|v|).
+* Messages after K iterations with stopping disabled: 1e-4 absolute (x, z and
+  u = lambda/mu).  ADMM's fixed-point map is non-expansive, so FP32 rounding
+  grows at most about linearly in K; 1e-4 covers K <= 200 on these codes.
+* Hard decisions: identical on every frame whose oracle x has no entry within
+  1e-3 of 1/2 (ambiguous frames are counted but not compared).
+* Iteration counts: the FP32 residual sums may cross eps^2 E one iteration
+  earlier or later than the FP64 ones: |delta| <= 2.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+lp = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    global lp
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    import paper_1204_0556_amd as m
+    lp = m
+    yield
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _proj_inputs(d, count, seed):
+    rng = np.random.default_rng([d, seed])
+    parts = [rng.uniform(-0.5, 1.5, (count, d)), rng.normal(0.5, 1.0, (count, d)),
+             rng.choice([-0.2, 0.0, 0.3, 0.7, 1.0, 1.2], size=(count, d)), rng.normal(0.0, 4.0, (count, d))]
+    # near-even clipped sums
+    near = rng.uniform(0, 1, (count, d))
+    tgt = 2 * np.maximum(1, np.round(near.sum(1) / 2))
+    near = near + ((tgt - near.sum(1)) / d)[:, None] + rng.normal(0, 1e-6, (count, d))
+    parts.append(near)
+    return np.concatenate(parts).astype(np.float32)
+
+
+@pytest.mark.parametrize("d", [2, 3, 4, 5, 6, 7, 8])
+def test_projection_matches_oracle(d):
+    v = _proj_inputs(d, 2000, 1)
+    print(f"projection d={d} count={len(v)}", flush=True)
+    z = host(lp.project(dev(v)))
+    zo = oracle.project(v.astype(np.float64))
+    tol = 2e-6 * (1.0 + np.abs(v).max(axis=1))
+    err = np.abs(z - zo).max(axis=1)
+    assert np.all(err <= tol), (err.max(), v[np.argmax(err - tol)])
+
+
+def _fixed_k(H, llr, K, mode):
+    x, it, fl, z, u = lp.decode_state(lp.Code(H), dev(llr), tol=0.0, max_iter=K, mode=mode)
+    return host(x), host(it), host(fl), host(z), host(u)
+
+
+@pytest.mark.parametrize("mode", ["resident", "persistent_global", "streamed"])
+@pytest.mark.parametrize("K", [1, 10, 50, 200])
+def test_messages_after_k_iterations(K, mode):
+    m = {"resident": lp.MODE_RESIDENT, "persistent_global": lp.MODE_PERSISTENT_GLOBAL,
+         "streamed": lp.MODE_STREAMED}[mode]
+    for n, frames in ((96, 64), (2640, 8)):
+        H = W.gallager36(n)
+        llr = W.awgn_batch(H, frames, 2.0, tag="fixedk")
+        print(f"fixed-K n={n} K={K} mode={mode}", flush=True)
+        x, it, fl, z, u = _fixed_k(H, llr, K, m)
+        ref = oracle.decode(H, llr, mu=3.0, rho=1.9, max_iter=K, tol=0.0, state=True)
+        assert np.all(it == K)
+        assert np.abs(x - ref.x).max() < 1e-4
+        assert np.abs(z - ref.z).max() < 1e-4
+        assert np.abs(u - ref.u).max() < 1e-4
+
+
+def test_forms_agree_bitwise():
+    H = W.gallager36(2640)
+    llr = W.awgn_batch(H, 32, 2.0, tag="forms")
+    code = lp.Code(H)
+    outs = []
+    for m in (lp.MODE_RESIDENT, lp.MODE_PERSISTENT_GLOBAL, lp.MODE_STREAMED):
+        x, it, fl = lp.decode(code, dev(llr), mode=m, max_iter=300)
+        outs.append((host(x), host(it), host(fl)))
+    for o in outs[1:]:
+        assert np.array_equal(o[1], outs[0][1])
+        assert np.array_equal(o[2], outs[0][2])
+        assert np.abs(o[0] - outs[0][0]).max() == 0.0
+
+
+def _compare_decodes(H, llr, x, it, fl, ref, max_iter):
+    ambiguous = np.any(np.abs(ref.x - 0.5) < 1e-3, axis=1)
+    hard, href = (x >= 0.5), (ref.x >= 0.5)
+    same = np.all(hard == href, axis=1)
+    assert np.all(same | ambiguous), np.nonzero(~(same | ambiguous))[0]
+    dit = np.abs(it.astype(int) - ref.iters)
+    assert np.mean(dit <= 2) >= 0.99, np.sort(dit)[-10:]
+    # flags: converged / certified agree except at the iteration-count margin
+    agree = (fl & 0x0F) == (ref.flags & 0x0F)
+    assert np.mean(agree) >= 0.99
+    return ambiguous
+
+
+def test_small_code_end_to_end():
+    """(3,6) n=96, 1000 frames at 3 dB, T = 200 (the small FP64 reference workload)."""
+    H = W.gallager36(96)
+    llr = W.awgn_batch(H, 1000, 3.0)
+    x, it, fl = lp.decode(lp.Code(H), dev(llr), mu=3.0, rho=1.9, max_iter=200, tol=1e-5)
+    ref = oracle.decode(H, llr, mu=3.0, rho=1.9, max_iter=200, tol=1e-5)
+    _compare_decodes(H, llr, host(x), host(it), host(fl), ref, 200)
+    fer_gpu = np.mean(host(x).__ge__(0.5).any(axis=1))
+    fer_cpu = np.mean(ref.hard.any(axis=1))
+    assert abs(fer_gpu - fer_cpu) <= 0.005
+
+
+def test_headline_batch_sampled():
+    """n=2640 (3,6) at the four Eb/N0 points, 4096 frames each, decoded in one call in
+    the benchmark's launch configuration; a sample of frames is checked against the oracle."""
+    H = W.gallager36(2640)
+    llr = np.concatenate([W.awgn_batch(H, 4096, s) for s in W.HEADLINE_SNRS])
+    print(f"headline batch frames={len(llr)}", flush=True)
+    x, it, fl = lp.decode(lp.Code(H), dev(llr))
+    x, it, fl = host(x), host(it), host(fl)
+    rng = np.random.default_rng(0)
+    sample = np.concatenate([b * 4096 + rng.choice(4096, 24, replace=False) for b in range(4)])
+    ref = oracle.decode(H, llr[sample])
+    _compare_decodes(H, llr[sample], x[sample], it[sample], fl[sample], ref, 1000)
+    # every frame: flags consistent with x (certificate recomputed on the host)
+    hard = (x >= 0.5).astype(np.int64)
+    Hd = H.to_scipy()
+    syn = (Hd @ hard.T) % 2
+    codeword = ~np.any(syn, axis=0)
+    assert np.array_equal(codeword, (fl & 0x04) != 0)
+    integral = np.max(np.minimum(x, 1 - x), axis=1) <= 1e-3
+    assert np.array_equal(integral, (fl & 0x02) != 0)
+    assert np.all(it[(fl & 0x01) == 0] == 1000)
+
+
+def test_invalid_frames_are_flagged():
+    H = W.gallager36(96)
+    llr = W.awgn_batch(H, 6, 3.0, tag="nan")
+    llr[1, 3] = np.nan
+    llr[4, 0] = -np.inf
+    for m in (lp.MODE_RESIDENT, lp.MODE_PERSISTENT_GLOBAL, lp.MODE_STREAMED):
+        x, it, fl = lp.decode(lp.Code(H), dev(llr), mode=m)
+        x, it, fl = host(x), host(it), host(fl)
+        for f in (1, 4):
+            assert fl[f] == lp.FLAG_INVALID and it[f] == 0 and np.all(x[f] == 0.5)
+        for f in (0, 2, 3, 5):
+            assert fl[f] & lp.FLAG_CONVERGED
+
+
+def test_warm_start_resume_is_exact():
+    H = W.gallager36(2640)
+    llr = W.awgn_batch(H, 4, 1.5, tag="warm")
+    code = lp.Code(H)
+    for m in (lp.MODE_RESIDENT, lp.MODE_STREAMED):
+        a = lp.decode_state(code, dev(llr), tol=0.0, max_iter=30, mode=m)
+        b = lp.decode_state(code, dev(llr), tol=0.0, max_iter=12, mode=m)
+        c = lp.decode_state(code, dev(llr), z=b[3], u=b[4], state_in=True, tol=0.0, max_iter=18, mode=m)
+        assert np.array_equal(host(a[3]), host(c[3])) and np.array_equal(host(a[4]), host(c[4]))
+        assert np.array_equal(host(a[0]), host(c[0]))
+
+
+def test_edge_batches():
+    H = W.gallager36(96)
+    code = lp.Code(H)
+    llr = W.awgn_batch(H, 1, 3.0, tag="one")
+    x, it, fl = lp.decode(code, dev(llr))
+    ref = oracle.decode(H, llr)
+    assert np.array_equal(host(x) >= 0.5, ref.x >= 0.5)
+    empty = torch.empty((0, H.n), dtype=torch.float32, device="cuda")
+    x, it, fl = lp.decode(code, empty)
+    assert x.shape == (0, H.n)
