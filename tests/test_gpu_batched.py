@@ -1,0 +1,129 @@
+"""GPU: batched uneven decoding (several codes, one persistent launch), large codes
+whose slot exchange lives in global memory, and FP16 message storage.
+
+"Same alone and in the mix" is checked bitwise: a frame's arithmetic depends only
+on its code's layout plan, never on which workgroup or launch decodes it.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+lp = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    global lp
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    import paper_1204_0556_amd as m
+    lp = m
+    yield
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _mixed(frames, seed=0, lengths=W.IRREGULAR_LENGTHS, lo=1.5, hi=3.0):
+    codes = [W.irregular_half(n) for n in lengths]
+    batch = W.mixed_batch(codes, frames, lo, hi, seed=seed)
+    flat, off = batch.flat_llr()
+    return codes, batch, flat, off
+
+
+def test_multi_code_frames_match_single_code_decodes_bitwise():
+    codes, batch, flat, off = _mixed(192)
+    handles = [lp.Code(H) for H in codes]
+    print(f"multi-code batch frames={batch.frames}", flush=True)
+    x, it, fl = lp.decode_multi(handles, batch.code_of_frame, off, dev(flat), off, flat.size)
+    x, it, fl = host(x), host(it), host(fl)
+    for c, H in enumerate(codes):
+        idx = np.nonzero(batch.code_of_frame == c)[0]
+        if idx.size == 0:
+            continue
+        llr = np.stack([batch.llr[f] for f in idx])
+        xs, its, fls = lp.decode(handles[c], dev(llr))
+        xs, its, fls = host(xs), host(its), host(fls)
+        for k, f in enumerate(idx):
+            assert np.array_equal(x[off[f]:off[f] + H.n], xs[k])
+            assert it[f] == its[k] and fl[f] == fls[k]
+
+
+def test_multi_code_against_oracle():
+    codes, batch, flat, off = _mixed(96, seed=1)
+    handles = [lp.Code(H) for H in codes]
+    x, it, fl = lp.decode_multi(handles, batch.code_of_frame, off, dev(flat), off, flat.size)
+    x, it, fl = host(x), host(it), host(fl)
+    for c, H in enumerate(codes):
+        idx = np.nonzero(batch.code_of_frame == c)[0]
+        if idx.size == 0:
+            continue
+        llr = np.stack([batch.llr[f] for f in idx])
+        ref = oracle.decode(H, llr)
+        for k, f in enumerate(idx):
+            xg = x[off[f]:off[f] + H.n]
+            ambiguous = np.any(np.abs(ref.x[k] - 0.5) < 1e-3)
+            assert ambiguous or np.array_equal(xg >= 0.5, ref.x[k] >= 0.5)
+            assert abs(int(it[f]) - int(ref.iters[k])) <= 2 or ambiguous
+
+
+def test_multi_code_rejects_bad_offsets():
+    codes, batch, flat, off = _mixed(4, seed=2, lengths=(576,))
+    handles = [lp.Code(H) for H in codes]
+    bad = off.copy()
+    bad[-1] = flat.size  # frame would read past the end
+    with pytest.raises(lp.LpdecError) as e:
+        lp.decode_multi(handles, batch.code_of_frame, bad, dev(flat), off, flat.size)
+    assert e.value.status == -1 and "outside llr_len" in str(e.value)
+
+
+@pytest.mark.parametrize("which", ["36", "48"])
+def test_large_codes_global_slots(which):
+    """n = 16384: the slot exchange exceeds LDS and goes through global scratch."""
+    H = W.gallager36(16384) if which == "36" else W.gallager48(16384)
+    llr = W.awgn_batch(H, 8, 2.5, tag="large")
+    code = lp.Code(H)
+    assert not code.info["resident_capable"]
+    print(f"large code {which} n={H.n} nnz={H.nnz}", flush=True)
+    for m in (lp.MODE_PERSISTENT_GLOBAL, lp.MODE_STREAMED):
+        x, it, fl, z, u = lp.decode_state(code, dev(llr), mode=m, tol=0.0, max_iter=20)
+        ref = oracle.decode(H, llr, max_iter=20, tol=0.0, state=True)
+        assert np.abs(host(x) - ref.x).max() < 1e-4
+        assert np.abs(host(z) - ref.z).max() < 1e-4 and np.abs(host(u) - ref.u).max() < 1e-4
+    x, it, fl = lp.decode(code, dev(llr))
+    ref = oracle.decode(H, llr)
+    assert np.array_equal(host(x) >= 0.5, ref.x >= 0.5)
+
+
+def test_fp16_storage_error_is_bounded():
+    """FP16 z/u storage with FP32 compute (streamed form) against FP32 storage and the
+    oracle after a fixed number of iterations.  FP16 keeps 11 significant bits; one
+    rounding per stored value and iteration gives |dz| <= 2^-11 per step."""
+    H = W.gallager36(2640)
+    llr = W.awgn_batch(H, 16, 2.5, tag="fp16")
+    code = lp.Code(H)
+    K = 20
+    ref = oracle.decode(H, llr, max_iter=K, tol=0.0, state=True)
+    x16, _, _, z16, u16 = lp.decode_state(code, dev(llr), mode=lp.MODE_STREAMED, storage=lp.STORAGE_FP16,
+                                          tol=0.0, max_iter=K)
+    x16, z16, u16 = host(x16), host(z16), host(u16)
+    ex, ez, eu = np.abs(x16 - ref.x).max(), np.abs(z16 - ref.z).max(), np.abs(u16 - ref.u).max()
+    print(f"fp16 storage K={K}: max|dx|={ex:.2e} max|dz|={ez:.2e} max|dlambda|={3 * eu:.2e}", flush=True)
+    assert ex < 2e-2 and ez < 2e-2 and eu < 5e-2
+    # full decodes: hard decisions agree with FP32 storage on nearly every frame
+    llr = W.awgn_batch(H, 256, 2.5, tag="fp16b")
+    x32, it32, _ = lp.decode(code, dev(llr), mode=lp.MODE_STREAMED)
+    x16, it16, fl16 = lp.decode(code, dev(llr), mode=lp.MODE_STREAMED, storage=lp.STORAGE_FP16)
+    agree = np.all((host(x32) >= 0.5) == (host(x16) >= 0.5), axis=1)
+    assert agree.mean() >= 0.99
