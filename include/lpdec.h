@@ -158,6 +158,80 @@ lpdec_status lpdec_decode_multi(const lpdec_code *const *codes, int32_t ncodes, 
  *   v, z  device [count*d] FP32, row-major (z may not alias v). */
 lpdec_status lpdec_project(int32_t d, int32_t count, const float *v, float *z, void *stream);
 
+/* ------------------------------------------------------------------------- */
+/* Serving: a request loop with continuous batching.
+ *
+ * Requests (frames of one code) are submitted from host memory at any time.  A
+ * dispatcher thread admits them in arrival order while their device footprint
+ * (4 n bytes of LLRs per frame) fits the budget, stages their LLRs into HBM and
+ * launches them on one of `max_inflight` streams, so requests that arrive while
+ * others are decoding start as soon as a stream and memory are free and run
+ * concurrently with them.  Each frame's completion is signalled by the kernel
+ * itself, so a request completes when its own frames do, not when its launch
+ * does.  Codes stay resident; a frame's result is the same alone or in the mix.
+ * Latency = submit to host-visible result. */
+typedef struct lpdec_server lpdec_server;
+
+#define LPDEC_EXECUTOR_GPU 0
+#define LPDEC_EXECUTOR_HOST_NULL 1 /* host-only executor for testing the scheduler without
+                                      a GPU: frames complete at once with x = 1/2,
+                                      iters = 0, flags = 0 (nothing is decoded)         */
+
+typedef struct {
+    int64_t budget_bytes;     /* device bytes for admitted frames (> 0)                 */
+    int32_t max_batch_frames; /* frames per launch (>= 1)                               */
+    int32_t max_inflight;     /* launches in flight at once (1..8)                      */
+    int32_t max_pending;      /* queued requests before submit returns LPDEC_EBUSY      */
+    int32_t executor;         /* LPDEC_EXECUTOR_*                                       */
+} lpdec_server_config;
+
+lpdec_server_config lpdec_server_default_config(void);
+
+/* codes: host [ncodes] code handles (GPU executor), or NULL with code_n: host [ncodes]
+ * code lengths (host-null executor only).  p: NULL = lpdec_default_params(); only the
+ * resident and persistent-global forms (FP32) serve.  The server keeps pointers to the
+ * codes: destroy the server before its codes.  Errors: LPDEC_EINVAL, LPDEC_ENOMEM,
+ * LPDEC_EDEVICE, LPDEC_EUNSUPPORTED. */
+lpdec_status lpdec_server_create(const lpdec_code *const *codes, const int32_t *code_n, int32_t ncodes,
+                                 const lpdec_params *p, const lpdec_server_config *cfg,
+                                 lpdec_server **out);
+
+/* Submit `frames` frames of code `code`; llr is host [frames*n] FP32, copied before
+ * return.  *ticket identifies the request.  Errors: LPDEC_EINVAL (bad code or frame
+ * count, or a request larger than the whole budget), LPDEC_EBUSY (max_pending queued). */
+lpdec_status lpdec_server_submit(lpdec_server *s, int32_t code, int32_t frames, const float *llr,
+                                 int64_t *ticket);
+
+#define LPDEC_REQ_QUEUED 0
+#define LPDEC_REQ_RUNNING 1
+#define LPDEC_REQ_DONE 2
+lpdec_status lpdec_server_poll(lpdec_server *s, int64_t ticket, int32_t *state);
+
+/* Wait up to timeout_s (< 0: forever) for a request, copy its results into host
+ * buffers (x [frames*n], iters [frames], flags [frames]; any may be NULL) and release
+ * it.  latency_s (may be NULL) receives submit-to-completion time.  LPDEC_EBUSY on
+ * timeout (the request stays live); LPDEC_EINVAL for an unknown ticket. */
+lpdec_status lpdec_server_wait(lpdec_server *s, int64_t ticket, double timeout_s, float *x, int32_t *iters,
+                               uint8_t *flags, double *latency_s);
+
+/* Withdraw a request that is still queued; LPDEC_EBUSY once it has been admitted. */
+lpdec_status lpdec_server_cancel(lpdec_server *s, int64_t ticket);
+
+typedef struct {
+    int64_t submitted, completed, cancelled, rejected;
+    int64_t frames_completed, bits_completed; /* coded bits */
+    int64_t inflight_bytes, peak_bytes;        /* admitted device footprint: now, maximum */
+    int64_t launches;
+    int32_t queued, running;
+    double p50_latency_s, p99_latency_s, mean_latency_s, max_latency_s;
+    double elapsed_s; /* first submit to last completion */
+} lpdec_server_stats;
+
+lpdec_status lpdec_server_get_stats(lpdec_server *s, lpdec_server_stats *st);
+
+/* Stop the dispatcher: running launches finish, queued requests are dropped.  NULL-safe. */
+void lpdec_server_destroy(lpdec_server *s);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char *lpdec_last_error(void);
 

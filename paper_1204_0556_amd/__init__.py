@@ -20,7 +20,8 @@ __all__ = [
     "Code", "decode", "decode_state", "decode_multi", "project", "default_params", "last_error",
     "LpdecError", "FLAG_CONVERGED", "FLAG_INTEGRAL", "FLAG_CODEWORD", "FLAG_CERTIFIED", "FLAG_INVALID",
     "MODE_AUTO", "MODE_RESIDENT", "MODE_STREAMED", "MODE_PERSISTENT_GLOBAL", "STORAGE_FP32", "STORAGE_FP16",
-    "MAX_CHECK_DEGREE", "library_path",
+    "MAX_CHECK_DEGREE", "library_path", "Server", "EXECUTOR_GPU", "EXECUTOR_HOST_NULL",
+    "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -30,6 +31,8 @@ FLAG_CONVERGED, FLAG_INTEGRAL, FLAG_CODEWORD, FLAG_CERTIFIED, FLAG_INVALID = 0x0
 MODE_AUTO, MODE_RESIDENT, MODE_STREAMED, MODE_PERSISTENT_GLOBAL = 0, 1, 2, 3
 STORAGE_FP32, STORAGE_FP16 = 0, 1
 STATE_IN, STATE_OUT = 0x1, 0x2
+EXECUTOR_GPU, EXECUTOR_HOST_NULL = 0, 1
+REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 MAX_CHECK_DEGREE = 8
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED", -5: "EBUSY"}
@@ -50,6 +53,21 @@ class _Info(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
                 ("min_check_degree", ctypes.c_int32), ("max_check_degree", ctypes.c_int32),
                 ("resident_capable", ctypes.c_int32), ("threads_per_frame", ctypes.c_int32)]
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("max_batch_frames", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("max_pending", ctypes.c_int32), ("executor", ctypes.c_int32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("cancelled", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("frames_completed", ctypes.c_int64),
+                ("bits_completed", ctypes.c_int64), ("inflight_bytes", ctypes.c_int64),
+                ("peak_bytes", ctypes.c_int64), ("launches", ctypes.c_int64), ("queued", ctypes.c_int32),
+                ("running", ctypes.c_int32), ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
+                ("mean_latency_s", ctypes.c_double), ("max_latency_s", ctypes.c_double),
+                ("elapsed_s", ctypes.c_double)]
 
 
 def _load():
@@ -76,6 +94,21 @@ def _load():
     lib.lpdec_decode_multi.restype = ctypes.c_int
     lib.lpdec_project.argtypes = [i32, i32, vp, vp, vp]
     lib.lpdec_project.restype = ctypes.c_int
+    lib.lpdec_server_default_config.restype = _ServerConfig
+    lib.lpdec_server_create.argtypes = [P(vp), P(i32), i32, P(_Params), P(_ServerConfig), P(vp)]
+    lib.lpdec_server_create.restype = ctypes.c_int
+    lib.lpdec_server_submit.argtypes = [vp, i32, i32, vp, P(i64)]
+    lib.lpdec_server_submit.restype = ctypes.c_int
+    lib.lpdec_server_poll.argtypes = [vp, i64, P(i32)]
+    lib.lpdec_server_poll.restype = ctypes.c_int
+    lib.lpdec_server_wait.argtypes = [vp, i64, ctypes.c_double, vp, vp, vp, P(ctypes.c_double)]
+    lib.lpdec_server_wait.restype = ctypes.c_int
+    lib.lpdec_server_cancel.argtypes = [vp, i64]
+    lib.lpdec_server_cancel.restype = ctypes.c_int
+    lib.lpdec_server_get_stats.argtypes = [vp, P(_ServerStats)]
+    lib.lpdec_server_get_stats.restype = ctypes.c_int
+    lib.lpdec_server_destroy.argtypes = [vp]
+    lib.lpdec_server_destroy.restype = None
     return lib
 
 
@@ -243,3 +276,87 @@ def project(v, stream=None):
     _check(_lib.lpdec_project(d, count, _dev_ptr(v, torch.float32, "v"), _dev_ptr(z, torch.float32, "z"),
                               _stream(stream)))
     return z
+
+
+class Server:
+    """Continuous-batching request loop (lpdec_server_*).  Requests are host numpy
+    arrays of LLRs; results come back as host numpy arrays.
+
+    codes: list of Code (GPU executor), or code_n: list of code lengths with
+    executor=EXECUTOR_HOST_NULL (scheduler tests without a GPU)."""
+
+    def __init__(self, codes=None, code_n=None, budget_bytes=None, max_batch_frames=None, max_inflight=None,
+                 max_pending=None, executor=EXECUTOR_GPU, **params):
+        cfg = _lib.lpdec_server_default_config()
+        if budget_bytes is not None: cfg.budget_bytes = int(budget_bytes)
+        if max_batch_frames is not None: cfg.max_batch_frames = int(max_batch_frames)
+        if max_inflight is not None: cfg.max_inflight = int(max_inflight)
+        if max_pending is not None: cfg.max_pending = int(max_pending)
+        cfg.executor = int(executor)
+        self._codes = list(codes) if codes is not None else None
+        if self._codes is not None:
+            self.n = [c.n for c in self._codes]
+            handles = (ctypes.c_void_p * len(self._codes))(*[c.handle.value for c in self._codes])
+            cn = None
+            k = len(self._codes)
+        else:
+            self.n = [int(v) for v in code_n]
+            handles = None
+            cn = (ctypes.c_int32 * len(self.n))(*self.n)
+            k = len(self.n)
+        p = _params(**params)
+        h = ctypes.c_void_p()
+        _check(_lib.lpdec_server_create(handles, cn, k, ctypes.byref(p), ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.config = {k2: getattr(cfg, k2) for k2, _ in _ServerConfig._fields_}
+
+    def submit(self, code: int, llr) -> int:
+        a = np.ascontiguousarray(llr, dtype=np.float32)
+        frames = a.size // self.n[code]
+        if frames * self.n[code] != a.size:
+            raise ValueError("llr size is not a multiple of n")
+        t = ctypes.c_int64()
+        _check(_lib.lpdec_server_submit(self._h, int(code), int(frames), a.ctypes.data_as(ctypes.c_void_p),
+                                        ctypes.byref(t)))
+        self._last_frames = getattr(self, "_last_frames", {})
+        self._last_frames[t.value] = (code, frames)
+        return t.value
+
+    def poll(self, ticket: int) -> int:
+        st = ctypes.c_int32()
+        _check(_lib.lpdec_server_poll(self._h, int(ticket), ctypes.byref(st)))
+        return st.value
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        """(x [frames, n], iters [frames], flags [frames], latency_s)."""
+        code, frames = self._last_frames[ticket]
+        n = self.n[code]
+        x = np.empty((frames, n), np.float32)
+        it = np.empty(frames, np.int32)
+        fl = np.empty(frames, np.uint8)
+        lat = ctypes.c_double()
+        _check(_lib.lpdec_server_wait(self._h, int(ticket), float(timeout), x.ctypes.data_as(ctypes.c_void_p),
+                                      it.ctypes.data_as(ctypes.c_void_p), fl.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.byref(lat)))
+        del self._last_frames[ticket]
+        return x, it, fl, lat.value
+
+    def cancel(self, ticket: int):
+        _check(_lib.lpdec_server_cancel(self._h, int(ticket)))
+        self._last_frames.pop(ticket, None)
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(_lib.lpdec_server_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lpdec_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

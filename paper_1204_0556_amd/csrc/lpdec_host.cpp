@@ -24,14 +24,13 @@
 
 #include "../../include/lpdec.h"
 #include "lpdec_internal.h"
+#include "lpdec_runtime.h"
 
 using namespace lpdec;
 
-namespace {
+static thread_local std::string g_last_error;
 
-thread_local std::string g_last_error;
-
-lpdec_status fail(lpdec_status st, const char *fmt, ...) {
+lpdec_status lpdec_fail(lpdec_status st, const char *fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -40,6 +39,10 @@ lpdec_status fail(lpdec_status st, const char *fmt, ...) {
     g_last_error = buf;
     return st;
 }
+
+namespace {
+
+#define fail lpdec_fail
 
 #define HIP_TRY(expr)                                                                          \
     do {                                                                                       \
@@ -76,62 +79,7 @@ hipError_t upload(const std::vector<T> &h, T **d) {
     return hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
-// Reusable device buffer that only grows.
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    hipError_t ensure(size_t need) {
-        if (need <= bytes) return hipSuccess;
-        if (p) {
-            hipError_t e = hipFree(p);
-            if (e != hipSuccess) return e;
-            p = nullptr;
-            bytes = 0;
-        }
-        need = std::max<size_t>(need, 256);
-        hipError_t e = hipMalloc(&p, need);
-        if (e == hipSuccess) bytes = need;
-        return e;
-    }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-};
-
 }  // namespace
-
-// Workspace for one decode call; serialised across streams with an event.
-struct Workspace {
-    std::mutex mu;
-    hipEvent_t last = nullptr;
-    DevBuf queue;      // persistent work counter
-    DevBuf codes;      // DevCode array (multi-code launches)
-    DevBuf frame_meta; // code_of_frame / offsets
-    DevBuf z, u, st, active, gslots, gstate;
-    int *host_active = nullptr; // pinned
-    ~Workspace() {
-        queue.release(); codes.release(); frame_meta.release();
-        z.release(); u.release(); st.release(); active.release(); gslots.release(); gstate.release();
-        if (host_active) (void)hipHostFree(host_active);
-        if (last) (void)hipEventDestroy(last);
-    }
-};
-
-struct lpdec_code {
-    DevCode dc{};          // host copy with device pointers
-    DevCode *d_dc = nullptr;
-    std::vector<void *> allocs;
-    int device = -1;
-    bool resident_ok = false;
-    LaunchConfig resident_cfg{};
-    Workspace ws;
-    ~lpdec_code() {
-        if (d_dc) (void)hipFree(d_dc);
-        for (void *p : allocs) (void)hipFree(p);
-    }
-};
 
 namespace {
 
@@ -393,12 +341,17 @@ struct WsGuard {
     }
 };
 
-// Core decode over a set of codes.  frames' code ids / offsets are either null
-// (single code, dense layout) or host arrays staged into the workspace.
-lpdec_status decode_core(const lpdec_code *const *codes, int ncodes, int nframes, const int32_t *code_of_frame,
-                         const int64_t *llr_off, const int64_t *x_off, const float *llr, const lpdec_params *pin,
-                         float *x_out, int32_t *iters_out, uint8_t *flags_out, float *z_state, float *u_state,
-                         int state_flags, void *stream_v) {
+}  // namespace
+
+// Core decode over a set of codes.  With llr_off / x_off (host arrays) the frames
+// are scattered in the llr / x buffers; code_of_frame (host) may be null when
+// all frames use codes[0].  `ws` defaults to the first code's workspace; `done`
+// (optional, host-visible) receives a completion flag per frame.
+lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int nframes,
+                               const int32_t *code_of_frame, const int64_t *llr_off, const int64_t *x_off,
+                               const float *llr, const lpdec_params *pin, float *x_out, int32_t *iters_out,
+                               uint8_t *flags_out, float *z_state, float *u_state, int state_flags, void *stream_v,
+                               Workspace *ws_in, int *done) {
     lpdec_params p = pin ? *pin : lpdec_default_params();
     lpdec_status st = check_params(&p);
     if (st != LPDEC_OK) return st;
@@ -432,13 +385,13 @@ lpdec_status decode_core(const lpdec_code *const *codes, int ncodes, int nframes
     }
     if (mode == LPDEC_MODE_PERSISTENT_GLOBAL) persistent_global_config(s, &cfg);
     if (mode == LPDEC_MODE_STREAMED) {
-        if (ncodes > 1 || code_of_frame)
-            return fail(LPDEC_EUNSUPPORTED, "the streamed form decodes one code per call");
+        if (ncodes > 1 || code_of_frame || llr_off || done)
+            return fail(LPDEC_EUNSUPPORTED, "the streamed form decodes one dense batch of one code per call");
         streamed_config(s, half, &cfg);
     }
 
-    WsGuard guard(c0->ws, stream);
-    Workspace &ws = c0->ws;
+    Workspace &ws = ws_in ? *ws_in : c0->ws;
+    WsGuard guard(ws, stream);
 
     // per-launch code table and frame metadata
     const DevCode *codes_dev = c0->d_dc;
@@ -448,24 +401,38 @@ lpdec_status decode_core(const lpdec_code *const *codes, int ncodes, int nframes
     fb.x_out = x_out;
     fb.iters_out = iters_out;
     fb.flags_out = flags_out;
-    if (ncodes > 1 || code_of_frame) {
-        std::vector<DevCode> tbl(ncodes);
-        for (int c = 0; c < ncodes; ++c) tbl[c] = codes[c]->dc;
-        HIP_TRY(ws.codes.ensure(sizeof(DevCode) * ncodes));
-        HIP_TRY(hipMemcpyAsync(ws.codes.p, tbl.data(), sizeof(DevCode) * ncodes, hipMemcpyHostToDevice, stream));
-        codes_dev = static_cast<const DevCode *>(ws.codes.p);
-        const size_t bytes = (size_t)nframes * (sizeof(int32_t) + 2 * sizeof(int64_t));
+    fb.done = done;
+    if (ncodes > 1 || code_of_frame || llr_off) {
+        // Metadata goes through pinned staging owned by the workspace.  The
+        // previous call on this workspace may still be copying from it, so wait
+        // for that call first (the source must outlive the asynchronous copy).
+        const size_t tbl_bytes = ((sizeof(DevCode) * ncodes + 255) / 256) * 256;
+        const size_t bytes = tbl_bytes + (size_t)nframes * (2 * sizeof(int64_t) + sizeof(int32_t));
+        if (ws.last) HIP_TRY(hipEventSynchronize(ws.last));
+        if (ws.host_meta_bytes < bytes) {
+            if (ws.host_meta) HIP_TRY(hipHostFree(ws.host_meta));
+            ws.host_meta = nullptr;
+            ws.host_meta_bytes = 0;
+            HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&ws.host_meta), bytes, hipHostMallocDefault));
+            ws.host_meta_bytes = bytes;
+        }
         HIP_TRY(ws.frame_meta.ensure(bytes));
-        char *base = static_cast<char *>(ws.frame_meta.p);
-        int64_t *d_loff = reinterpret_cast<int64_t *>(base);
-        int64_t *d_xoff = d_loff + nframes;
-        int32_t *d_cof = reinterpret_cast<int32_t *>(d_xoff + nframes);
-        HIP_TRY(hipMemcpyAsync(d_loff, llr_off, sizeof(int64_t) * nframes, hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipMemcpyAsync(d_xoff, x_off, sizeof(int64_t) * nframes, hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipMemcpyAsync(d_cof, code_of_frame, sizeof(int32_t) * nframes, hipMemcpyHostToDevice, stream));
-        fb.llr_off = d_loff;
-        fb.x_off = d_xoff;
-        fb.code_of_frame = d_cof;
+        char *h = ws.host_meta;
+        for (int c = 0; c < ncodes; ++c) std::memcpy(h + sizeof(DevCode) * c, &codes[c]->dc, sizeof(DevCode));
+        int64_t *h_loff = reinterpret_cast<int64_t *>(h + tbl_bytes);
+        int64_t *h_xoff = h_loff + nframes;
+        int32_t *h_cof = reinterpret_cast<int32_t *>(h_xoff + nframes);
+        for (int f = 0; f < nframes; ++f) {
+            h_loff[f] = llr_off ? llr_off[f] : (int64_t)f * codes[0]->dc.n;
+            h_xoff[f] = x_off ? x_off[f] : (int64_t)f * codes[0]->dc.n;
+            h_cof[f] = code_of_frame ? code_of_frame[f] : 0;
+        }
+        HIP_TRY(hipMemcpyAsync(ws.frame_meta.p, h, bytes, hipMemcpyHostToDevice, stream));
+        char *d = static_cast<char *>(ws.frame_meta.p);
+        codes_dev = reinterpret_cast<const DevCode *>(d);
+        fb.llr_off = reinterpret_cast<const int64_t *>(d + tbl_bytes);
+        fb.x_off = fb.llr_off + nframes;
+        if (code_of_frame) fb.code_of_frame = reinterpret_cast<const int32_t *>(fb.x_off + nframes);
     }
     IterParams ip{};
     ip.mu_inv = 1.0f / p.mu;
@@ -567,8 +534,6 @@ lpdec_status decode_core(const lpdec_code *const *codes, int ncodes, int nframes
     return LPDEC_OK;
 }
 
-}  // namespace
-
 // ---------------------------------------------------------------------------
 // C ABI
 
@@ -625,8 +590,8 @@ lpdec_status lpdec_code_get_info(const lpdec_code *code, lpdec_code_info *info) 
 lpdec_status lpdec_decode(const lpdec_code *code, int32_t batch, const float *llr, const lpdec_params *p,
                           float *x_out, int32_t *iters_out, uint8_t *flags_out, void *stream) {
     if (!code) return fail(LPDEC_EINVAL, "code must not be NULL");
-    return decode_core(&code, 1, batch, nullptr, nullptr, nullptr, llr, p, x_out, iters_out, flags_out, nullptr,
-                       nullptr, 0, stream);
+    return lpdec_decode_core(&code, 1, batch, nullptr, nullptr, nullptr, llr, p, x_out, iters_out, flags_out,
+                             nullptr, nullptr, 0, stream, nullptr, nullptr);
 }
 
 lpdec_status lpdec_decode_state(const lpdec_code *code, int32_t batch, const float *llr, const lpdec_params *p,
@@ -634,8 +599,8 @@ lpdec_status lpdec_decode_state(const lpdec_code *code, int32_t batch, const flo
                                 float *u_state, int32_t state_flags, void *stream) {
     if (!code) return fail(LPDEC_EINVAL, "code must not be NULL");
     if (state_flags & ~(LPDEC_STATE_IN | LPDEC_STATE_OUT)) return fail(LPDEC_EINVAL, "unknown state_flags bits");
-    return decode_core(&code, 1, batch, nullptr, nullptr, nullptr, llr, p, x_out, iters_out, flags_out, z_state,
-                       u_state, state_flags, stream);
+    return lpdec_decode_core(&code, 1, batch, nullptr, nullptr, nullptr, llr, p, x_out, iters_out, flags_out,
+                             z_state, u_state, state_flags, stream, nullptr, nullptr);
 }
 
 lpdec_status lpdec_decode_multi(const lpdec_code *const *codes, int32_t ncodes, int32_t nframes,
@@ -662,8 +627,8 @@ lpdec_status lpdec_decode_multi(const lpdec_code *const *codes, int32_t ncodes, 
     lpdec_params pp = p ? *p : lpdec_default_params();
     if (pp.mode == LPDEC_MODE_STREAMED || pp.storage == LPDEC_STORAGE_FP16)
         return fail(LPDEC_EUNSUPPORTED, "multi-code decoding runs in one persistent launch (FP32)");
-    return decode_core(codes, ncodes, nframes, code_of_frame, llr_offset, x_offset, llr, &pp, x_out, iters_out,
-                       flags_out, nullptr, nullptr, 0, stream);
+    return lpdec_decode_core(codes, ncodes, nframes, code_of_frame, llr_offset, x_offset, llr, &pp, x_out,
+                             iters_out, flags_out, nullptr, nullptr, 0, stream, nullptr, nullptr);
 }
 
 lpdec_status lpdec_project(int32_t d, int32_t count, const float *v, float *z, void *stream) {

@@ -57,6 +57,7 @@ struct FrameBatch {
     int *iters_out;
     uint8_t *flags_out;
     int *queue;                 // device work counter (persistent kernels)
+    int *done;                  // optional [nframes] completion flags (host-visible), set last
 };
 
 struct IterParams {

@@ -358,9 +358,14 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             if (__syncthreads_or(bad)) {
                 for (int i = tid; i < C.n; i += NT)
                     fb.x_out[(fb.x_off ? fb.x_off[f] : (int64_t)f * C.n) + i] = 0.5f;
+                __syncthreads();
                 if (tid == 0) {
                     fb.iters_out[f] = 0;
                     fb.flags_out[f] = 0x80;
+                    if (fb.done) {
+                        __threadfence_system();
+                        __hip_atomic_store(fb.done + f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    }
                 }
                 __syncthreads();
                 continue;
@@ -594,6 +599,12 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             if ((fl & 0x07) == 0x07) fl |= 0x08;
             fb.iters_out[f] = iters;
             fb.flags_out[f] = fl;
+            if (fb.done) {
+                // every thread's x store precedes the barrier above; publish them
+                // to the host before the completion flag
+                __threadfence_system();
+                __hip_atomic_store(fb.done + f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
         }
         // state export (CSR edge order)
         if (sio.z_out) {

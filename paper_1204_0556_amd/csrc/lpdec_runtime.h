@@ -1,0 +1,82 @@
+// Host-side runtime types shared by the decoder entry points (lpdec_host.cpp)
+// and the serving loop (lpdec_server.cpp).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "../../include/lpdec.h"
+#include "lpdec_internal.h"
+
+// Reusable device buffer that only grows.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t need) {
+        if (need <= bytes) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess) return e;
+            p = nullptr;
+            bytes = 0;
+        }
+        need = std::max<size_t>(need, 256);
+        hipError_t e = hipMalloc(&p, need);
+        if (e == hipSuccess) bytes = need;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+
+// Workspace for one decode call; serialised across streams with an event.
+struct Workspace {
+    std::mutex mu;
+    hipEvent_t last = nullptr;
+    DevBuf queue;      // persistent work counter
+    DevBuf codes;      // DevCode array (multi-code launches)
+    DevBuf frame_meta; // code_of_frame / offsets
+    DevBuf z, u, st, active, gslots, gstate;
+    int *host_active = nullptr; // pinned
+    char *host_meta = nullptr;  // pinned staging for per-call metadata
+    size_t host_meta_bytes = 0;
+    ~Workspace() {
+        queue.release(); codes.release(); frame_meta.release();
+        z.release(); u.release(); st.release(); active.release(); gslots.release(); gstate.release();
+        if (host_active) (void)hipHostFree(host_active);
+        if (host_meta) (void)hipHostFree(host_meta);
+        if (last) (void)hipEventDestroy(last);
+    }
+};
+
+struct lpdec_code {
+    lpdec::DevCode dc{};   // host copy with device pointers
+    lpdec::DevCode *d_dc = nullptr;
+    std::vector<void *> allocs;
+    int device = -1;
+    bool resident_ok = false;
+    lpdec::LaunchConfig resident_cfg{};
+    Workspace ws;
+    ~lpdec_code() {
+        if (d_dc) (void)hipFree(d_dc);
+        for (void *p : allocs) (void)hipFree(p);
+    }
+};
+
+
+// Sets the thread-local message returned by lpdec_last_error() and returns st.
+lpdec_status lpdec_fail(lpdec_status st, const char *fmt, ...);
+
+// Decode core shared by every entry point (see lpdec_host.cpp).
+lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int nframes,
+                               const int32_t *code_of_frame, const int64_t *llr_off, const int64_t *x_off,
+                               const float *llr, const lpdec_params *pin, float *x_out, int32_t *iters_out,
+                               uint8_t *flags_out, float *z_state, float *u_state, int state_flags, void *stream_v,
+                               Workspace *ws_in, int *done);
