@@ -178,7 +178,24 @@ bool lpdec_server::collect() {
             finish_frame(s.frames[f].first, s.frames[f].second, s.iters[f], s.flags[f]);
             changed = true;
         }
-        if (s.remaining == 0 && (!gpu || hipEventQuery(s.ev) == hipSuccess)) {
+        if (s.remaining > 0 && gpu) {
+            const hipError_t q = hipEventQuery(s.ev);
+            if (q != hipErrorNotReady) {
+                // The launch is over (or failed) but some frames never raised their
+                // flag: rescan once, then fail the rest as not decoded.
+                for (size_t f = 0; f < s.frames.size(); ++f) {
+                    if (s.seen[f]) continue;
+                    const bool ok = q == hipSuccess && __atomic_load_n(s.done + f, __ATOMIC_ACQUIRE);
+                    if (!ok && thread_error.empty()) thread_error = "a launch ended without completing its frames";
+                    s.seen[f] = 1;
+                    --s.remaining;
+                    finish_frame(s.frames[f].first, s.frames[f].second, ok ? s.iters[f] : 0,
+                                 ok ? s.flags[f] : (uint8_t)0x80);
+                }
+                changed = true;
+            }
+        }
+        if (s.remaining == 0 && (!gpu || hipEventQuery(s.ev) != hipErrorNotReady)) {
             s.busy = false;
             s.frames.clear();
             changed = true;
