@@ -227,6 +227,7 @@ lpdec_status build_plan(int32_t m, int32_t n, int64_t nnz, const int32_t *row_pt
 // Launch-shape planning for a set of codes decoded together.
 struct Shape {
     int waves = 0, cpt = 0, nmax = 0, Emax = 0, Eint_max = 0, dclass = 0;
+    int dv = 0;  // common variable degree of all codes (0 if mixed)
 };
 
 Shape shape_of(const lpdec_code *const *codes, int ncodes) {
@@ -242,6 +243,9 @@ Shape shape_of(const lpdec_code *const *codes, int ncodes) {
         all6 = all6 && D.dmin == 6 && D.dmax == 6;
     }
     s.dclass = all6 ? 0 : 1;
+    s.dv = (codes[0]->dc.nvc == 1) ? codes[0]->dc.vc_deg[0] : 0;
+    for (int c = 1; c < ncodes; ++c)
+        if (codes[c]->dc.nvc != 1 || codes[c]->dc.vc_deg[0] != s.dv) s.dv = 0;
     return s;
 }
 
@@ -263,6 +267,7 @@ bool resident_config(const Shape &s, LaunchConfig *cfg) {
     cfg->cpt_tmpl = 2;
     cfg->vpt_tmpl = vpt <= 4 ? 4 : 8;
     cfg->dclass = 0;
+    cfg->dv = (s.dv == 3) ? 3 : 0;
     cfg->lds_slots = true;
     cfg->half = false;
     cfg->threads = threads;

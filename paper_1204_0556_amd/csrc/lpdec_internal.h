@@ -95,6 +95,7 @@ struct LaunchConfig {
     int cpt_tmpl;      // register-held chunks per wave: 0 (re-read), 2 or 4
     int vpt_tmpl;      // register-held variables per thread (resident form): 4 or 8
     int dclass;        // 0: degrees exactly 6; 1: degrees 2..8
+    int dv;            // every variable has this degree (0: mixed), resident form
     bool lds_slots;    // slots in LDS (else global scratch)
     bool half;         // fp16 state storage (streamed only)
     int threads;       // workgroup size

@@ -104,12 +104,17 @@ __device__ __forceinline__ void project_pp(const float *v, float *z) {
 #pragma unroll
     for (int k = 0; k < D; ++k) sv[k] = v[k];
     sort_desc<D>(sv);
-    float g0 = 0.0f;  // f_r^T zhat, signs by sorted position
+    // f_r^T zhat = 2 (sum of the r+1 largest clipped entries) - sum of all of them
+    float top = clamp01(sv[0]);
+    {
+        float pref = top;
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        const float c = clamp01(sv[k]);
-        g0 += ((float)k <= rf) ? c : -c;
+        for (int k = 1; k < D; ++k) {
+            pref += clamp01(sv[k]);
+            if ((k & 1) == 0) top = (rf == (float)k) ? pref : top;
+        }
     }
+    const float g0 = 2.0f * top - s;
     if (g0 <= rf) return;  // zhat lies in PP_d
     // t1 = v_(r+1), t2 = v_(r+2) (1-based order statistics); r is even
     float t1 = sv[0];
@@ -138,7 +143,7 @@ __device__ __forceinline__ void project_pp(const float *v, float *z) {
     }
     beta = fminf(fmaxf(beta, 0.0f), beta_max);
 #pragma unroll
-    for (int k = 0; k < D; ++k) z[k] = clamp01(v[k] - ((v[k] >= t1) ? beta : -beta));
+    for (int k = 0; k < D; ++k) z[k] = clamp01(fmaf((v[k] >= t1) ? -1.0f : 1.0f, beta, v[k]));
 }
 
 // ---------------------------------------------------------------------------
@@ -186,10 +191,25 @@ hipError_t launch_fill_i32(int *p, int value, int count, hipStream_t stream) {
 // ---------------------------------------------------------------------------
 // Workgroup helpers.
 
+// Sum over the 64 lanes of a wavefront, returned in every lane.  DPP steps sum
+// each row of 16 lanes (quad_perm xor 1, xor 2, half-row mirror, row mirror; every
+// lane of a row ends with bitwise the same value since float addition commutes),
+// then the four row sums are read from lanes 0/16/32/48 and added in a fixed order.
+// No LDS traffic, and the same order in every wave and every kernel form.
+template <int CTRL>
+__device__ __forceinline__ float dpp_shift(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
 __device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, kWave);
-    return x;
+    x += dpp_shift<0xB1>(x);   // quad_perm [1,0,3,2]
+    x += dpp_shift<0x4E>(x);   // quad_perm [2,3,0,1]
+    x += dpp_shift<0x141>(x);  // row_half_mirror
+    x += dpp_shift<0x140>(x);  // row_mirror
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
+    return (r0 + r1) + (r2 + r3);
 }
 
 template <int DMIN, int DMAX, typename F>
@@ -267,7 +287,8 @@ __device__ __forceinline__ void st_state(void *p, size_t i, float a) {
 // check l of each of them.  CPT > 0 keeps those chunks' z,u (and packed edge
 // metadata) in registers; CPT == 0 walks the chunks and re-reads state.
 // Variable side: thread t owns internal variables t, t + NT, ...
-template <int DMIN, int DMAX, int CPT, int VPT, bool RES, bool PERSIST, bool LDS_SLOTS, bool HALF, int MAXT>
+template <int DMIN, int DMAX, int CPT, int VPT, bool RES, bool PERSIST, bool LDS_SLOTS, bool HALF, int MAXT,
+          int DV>
 __global__ void __launch_bounds__(MAXT)
 k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateIO sio, StreamArgs sa,
          int lds_E, int slot_stride, int state_stride) {
@@ -291,6 +312,9 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
     int cdeg[NC], coff[NC];
     bool cval[NC];
     float vg[VPT > 0 ? VPT : 1];
+    // owned variables' slot blocks (resident form; DV > 0: every variable has degree DV)
+    int vslot[VPT > 0 ? VPT : 1], vdeg[VPT > 0 ? VPT : 1];
+    float vinv[VPT > 0 ? VPT : 1];
     int cur_code = -1;
 
     int next_f = blockIdx.x;
@@ -333,6 +357,17 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
 #pragma unroll
                     for (int e = 0; e < DMAX; ++e)
                         meta[k][e] = (cval[k] && e < cdeg[k]) ? C.edge_meta[coff[k] + e * kWave + lane] : 0u;
+                }
+                if constexpr (VPT > 0 && DV == 0) {
+#pragma unroll
+                    for (int t = 0; t < VPT; ++t) {
+                        const int i = tid + t * NT;
+                        VarLoc L{0, 0, 0.0f};
+                        if (i < C.n) L = var_loc(C, i);
+                        vslot[t] = L.slot0;
+                        vdeg[t] = L.deg;
+                        vinv[t] = L.inv;
+                    }
                 }
                 cur_code = ci;
             }
@@ -451,11 +486,23 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         };
 
         auto phase_b = [&]() {
-            if constexpr (VPT > 0) {
+            if constexpr (VPT > 0 && DV > 0) {
+                constexpr float inv = 1.0f / (float)DV;
 #pragma unroll
                 for (int t = 0; t < VPT; ++t) {
                     const int i = tid + t * NT;
-                    if (i < C.n) xs[i] = x_update(slots, var_loc(C, i), vg[t]);
+                    if (i < C.n) {
+                        float acc = 0.0f;
+#pragma unroll
+                        for (int p = 0; p < DV; ++p) acc += slots[DV * i + p];
+                        xs[i] = clamp01((acc - vg[t]) * inv);
+                    }
+                }
+            } else if constexpr (VPT > 0) {
+#pragma unroll
+                for (int t = 0; t < VPT; ++t) {
+                    const int i = tid + t * NT;
+                    if (i < C.n) xs[i] = x_update(slots, VarLoc{vslot[t], vdeg[t], vinv[t]}, vg[t]);
                 }
             } else {
                 for (int i = tid; i < C.n; i += NT) {
@@ -688,11 +735,12 @@ hipError_t launch_stream_init(const DevCode *codes_dev, int nframes, const Launc
 // ---------------------------------------------------------------------------
 // Instantiation table.
 
-template <int DMIN, int DMAX, int CPT, int VPT, bool RES, bool PERSIST, bool LDS, bool HALF, int MAXT = kMaxThreads>
+template <int DMIN, int DMAX, int CPT, int VPT, bool RES, bool PERSIST, bool LDS, bool HALF, int MAXT = kMaxThreads,
+          int DV = 0>
 static hipError_t go(const LaunchConfig &cfg, const DevCode *codes, const FrameBatch &fb, const IterParams &ip,
                      const StateIO &sio, const StreamArgs &sa, hipStream_t stream, int *occ) {
     if (cfg.threads > MAXT) return hipErrorInvalidConfiguration;
-    auto kern = k_decode<DMIN, DMAX, CPT, VPT, RES, PERSIST, LDS, HALF, MAXT>;
+    auto kern = k_decode<DMIN, DMAX, CPT, VPT, RES, PERSIST, LDS, HALF, MAXT, DV>;
     if (cfg.lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg.lds_bytes);
@@ -711,9 +759,10 @@ static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const 
 #define LPD_GO(...) return go<DMIN, DMAX, __VA_ARGS__>(cfg, codes, fb, ip, sio, sa, stream, occ)
     switch (cfg.form) {
         case Form::Resident:
+            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4 && cfg.dv == 3) LPD_GO(2, 4, true, true, true, false, 768, 3);
+            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8 && cfg.dv == 3) LPD_GO(2, 8, true, true, true, false, 768, 3);
             if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4) LPD_GO(2, 4, true, true, true, false, 768);
             if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8) LPD_GO(2, 8, true, true, true, false, 768);
-            if (cfg.cpt_tmpl == 4 && cfg.vpt_tmpl == 8) LPD_GO(4, 8, true, true, true, false, 512);
             break;
         case Form::PersistentGlobal:
             if (cfg.lds_slots) {
