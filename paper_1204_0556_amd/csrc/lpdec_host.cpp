@@ -147,6 +147,17 @@ lpdec_status build_plan(int32_t m, int32_t n, int64_t nnz, const int32_t *row_pt
         }
         slot += d;
     }
+    D.dv = (D.nvc == 1) ? D.vc_deg[0] : 0;
+    D.dv_inv = (D.nvc == 1) ? D.vc_inv[0] : 0.0f;
+    std::vector<int2> vinfo(n);
+    for (int c = 0; c < D.nvc; ++c) {
+        const int end = (c + 1 < D.nvc) ? D.vc_start[c + 1] : n;
+        for (int i = D.vc_start[c]; i < end; ++i) {
+            vinfo[i].x = (D.vc_slot0[c] + (i - D.vc_start[c]) * D.vc_deg[c]) | (D.vc_deg[c] << 24);
+            float inv = D.vc_inv[c];
+            std::memcpy(&vinfo[i].y, &inv, sizeof inv);
+        }
+    }
     for (int c = D.nvc; c <= 8; ++c) D.vc_start[c] = n;
     for (int c = D.nvc; c < 8; ++c) {
         D.vc_slot0[c] = slot;
@@ -200,6 +211,7 @@ lpdec_status build_plan(int32_t m, int32_t n, int64_t nnz, const int32_t *row_pt
 
     int *d_cdeg, *d_coff, *d_ccnt, *d_ecsr, *d_vorig;
     uint32_t *d_meta;
+    int2 *d_vinfo;
     hipError_t e = hipGetDevice(&code->device);
     if (e != hipSuccess) return fail(LPDEC_EDEVICE, "no HIP device: %s", hipGetErrorString(e));
     if ((e = upload(chunk_deg, &d_cdeg)) != hipSuccess ||
@@ -207,10 +219,12 @@ lpdec_status build_plan(int32_t m, int32_t n, int64_t nnz, const int32_t *row_pt
         (code->allocs.push_back(d_coff), (e = upload(chunk_cnt, &d_ccnt)) != hipSuccess) ||
         (code->allocs.push_back(d_ccnt), (e = upload(meta, &d_meta)) != hipSuccess) ||
         (code->allocs.push_back(d_meta), (e = upload(ecsr, &d_ecsr)) != hipSuccess) ||
-        (code->allocs.push_back(d_ecsr), (e = upload(vorder, &d_vorig)) != hipSuccess))
+        (code->allocs.push_back(d_ecsr), (e = upload(vorder, &d_vorig)) != hipSuccess) ||
+        (code->allocs.push_back(d_vorig), (e = upload(vinfo, &d_vinfo)) != hipSuccess))
         return fail(e == hipErrorOutOfMemory ? LPDEC_ENOMEM : LPDEC_EDEVICE, "uploading the code: %s",
                     hipGetErrorString(e));
-    code->allocs.push_back(d_vorig);
+    code->allocs.push_back(d_vinfo);
+    D.var_info = d_vinfo;
     D.chunk_deg = d_cdeg;
     D.chunk_off = d_coff;
     D.chunk_cnt = d_ccnt;
@@ -228,6 +242,7 @@ lpdec_status build_plan(int32_t m, int32_t n, int64_t nnz, const int32_t *row_pt
 struct Shape {
     int waves = 0, cpt = 0, nmax = 0, Emax = 0, Eint_max = 0, dclass = 0;
     int dv = 0;  // common variable degree of all codes (0 if mixed)
+    bool permuted = false;  // some code renumbers its variables
 };
 
 Shape shape_of(const lpdec_code *const *codes, int ncodes) {
@@ -241,6 +256,7 @@ Shape shape_of(const lpdec_code *const *codes, int ncodes) {
         s.Emax = std::max(s.Emax, D.E);
         s.Eint_max = std::max(s.Eint_max, D.E_int);
         all6 = all6 && D.dmin == 6 && D.dmax == 6;
+        s.permuted = s.permuted || !D.var_identity;
     }
     s.dclass = all6 ? 0 : 1;
     s.dv = (codes[0]->dc.nvc == 1) ? codes[0]->dc.vc_deg[0] : 0;
@@ -268,7 +284,7 @@ bool resident_config(const Shape &s, LaunchConfig *cfg) {
     cfg->vpt_tmpl = vpt <= 4 ? 4 : 8;
     cfg->dclass = 0;
     cfg->dv = (s.dv == 3) ? 3 : 0;
-    cfg->lds_slots = true;
+    cfg->slot_mode = 1;
     cfg->half = false;
     cfg->threads = threads;
     cfg->lds_bytes = lds;
@@ -278,31 +294,39 @@ bool resident_config(const Shape &s, LaunchConfig *cfg) {
     return true;
 }
 
+// Where the slot exchange of the non-resident forms lives: LDS float slots when
+// 4 (E + n) bytes fit, else LDS fixed-point accumulators (8 n bytes), else global.
+int slot_mode_for(const Shape &s, size_t *lds_bytes) {
+    const size_t lds_slots = 4 * ((size_t)s.Emax + s.nmax), lds_acc = 8 * (size_t)s.nmax;
+    if (lds_slots + kStaticLds <= kLdsLimit) { *lds_bytes = lds_slots; return 1; }
+    if (lds_acc + kStaticLds <= kLdsLimit) { *lds_bytes = lds_acc; return 2; }
+    *lds_bytes = 4 * (size_t)s.nmax;
+    return 0;
+}
+
 void persistent_global_config(const Shape &s, LaunchConfig *cfg) {
-    const size_t lds_all = 4 * ((size_t)s.Emax + s.nmax);
     cfg->form = Form::PersistentGlobal;
     cfg->cpt_tmpl = 0;
     cfg->vpt_tmpl = 0;
     cfg->dclass = s.dclass;
-    cfg->lds_slots = lds_all + kStaticLds <= kLdsLimit;
+    cfg->dv = 0;
+    cfg->slot_mode = slot_mode_for(s, &cfg->lds_bytes);
     cfg->half = false;
     cfg->threads = s.waves * kWave;
-    cfg->lds_bytes = cfg->lds_slots ? lds_all : 4 * (size_t)s.nmax;
     cfg->lds_E = s.Emax;
     cfg->slot_stride = s.Emax;
     cfg->state_stride = s.Eint_max;
 }
 
 void streamed_config(const Shape &s, bool half, LaunchConfig *cfg) {
-    const size_t lds_all = 4 * ((size_t)s.Emax + s.nmax);
     cfg->form = Form::Streamed;
-    cfg->lds_slots = lds_all + kStaticLds <= kLdsLimit;
-    cfg->cpt_tmpl = (cfg->lds_slots && s.cpt <= 2) ? 2 : 0;
+    cfg->slot_mode = slot_mode_for(s, &cfg->lds_bytes);
+    cfg->cpt_tmpl = (cfg->slot_mode == 1 && s.cpt <= 2) ? 2 : 0;
     cfg->vpt_tmpl = 0;
     cfg->dclass = s.dclass;
+    cfg->dv = 0;
     cfg->half = half;
     cfg->threads = s.waves * kWave;
-    cfg->lds_bytes = cfg->lds_slots ? lds_all : 4 * (size_t)s.nmax;
     cfg->lds_E = s.Emax;
     cfg->slot_stride = s.Emax;
     cfg->state_stride = 0;
@@ -461,10 +485,20 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
         fb.queue = static_cast<int *>(ws.queue.p);
         HIP_TRY(launch_fill_i32(fb.queue, 0, 1, stream));
         if (cfg.form == Form::PersistentGlobal) {
+            if (s.permuted) {
+                HIP_TRY(ws.gmu.ensure(sizeof(float) * (size_t)cfg.grid * s.nmax));
+                sa.gmu = static_cast<float *>(ws.gmu.p);
+                sa.gmu_stride = s.nmax;
+            }
             HIP_TRY(ws.gstate.ensure(2 * sizeof(float) * (size_t)cfg.grid * cfg.state_stride));
             sa.z = ws.gstate.p;
             sa.u = static_cast<float *>(ws.gstate.p) + (size_t)cfg.grid * cfg.state_stride;
-            if (!cfg.lds_slots) {
+            if (cfg.slot_mode == 2) {
+                HIP_TRY(ws.gxprev.ensure(sizeof(unsigned) * (size_t)cfg.grid * s.nmax));
+                sa.gxprev = static_cast<unsigned *>(ws.gxprev.p);
+                sa.gmu_stride = s.nmax;
+            }
+            if (cfg.slot_mode == 0) {
                 HIP_TRY(ws.gslots.ensure(sizeof(float) * (size_t)cfg.grid * cfg.slot_stride));
                 sa.gslots = static_cast<float *>(ws.gslots.p);
             }
@@ -484,8 +518,13 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
         sa.u = ws.u.p;
         sa.st = static_cast<StreamFrame *>(ws.st.p);
         sa.active_count = static_cast<int *>(ws.active.p);
+        if (s.permuted) {
+            HIP_TRY(ws.gmu.ensure(sizeof(float) * (size_t)nframes * s.nmax));
+            sa.gmu = static_cast<float *>(ws.gmu.p);
+            sa.gmu_stride = s.nmax;
+        }
         cfg.grid = occupancy_grid(cfg, nframes);
-        if (!cfg.lds_slots) {
+        if (cfg.slot_mode == 0) {
             HIP_TRY(ws.gslots.ensure(sizeof(float) * (size_t)cfg.grid * cfg.slot_stride));
             sa.gslots = static_cast<float *>(ws.gslots.p);
         }

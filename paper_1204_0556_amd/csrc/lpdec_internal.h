@@ -30,6 +30,8 @@ struct DevCode {
     int cpt;              // chunks per wave (chunk c belongs to wave c % waves)
     int dmin, dmax;
     int var_identity;     // internal variable order equals the original one
+    int dv;               // common variable degree (0 if degrees differ)
+    float dv_inv;         // 1 / dv
     // Variables sorted by decreasing degree form nvc <= 8 classes: class c holds
     // internal variables [vc_start[c], vc_start[c+1]) of degree vc_deg[c], whose
     // slots start at vc_slot0[c].
@@ -44,6 +46,7 @@ struct DevCode {
     const uint32_t *edge_meta;// [E_int] (slot << 16) | internal variable (0 on padding)
     const int *edge_csr;      // [E_int] CSR edge id (-1 on padding)
     const int *var_orig;      // [n] internal -> original variable index
+    const int2 *var_info;     // [n] {slot0 | deg << 24, bits of 1/deg} per internal variable
 };
 
 // Frames of one launch.
@@ -85,6 +88,9 @@ struct StreamArgs {
     StreamFrame *st;        // [frames]
     int *active_count;      // device counter of frames still running after this launch
     float *gslots;          // [workgroups][slot_stride] slot scratch when slots live in global memory
+    float *gmu;             // gamma/mu in internal variable order: [workgroups or frames][gmu_stride]
+    unsigned *gxprev;       // accumulator mode, persistent form: previous x bits [workgroups][gmu_stride]
+    int gmu_stride;
 };
 
 // Launchers (defined in lpdec_kernels.hip).  Return hipSuccess or the launch error.
@@ -96,7 +102,7 @@ struct LaunchConfig {
     int vpt_tmpl;      // register-held variables per thread (resident form): 4 or 8
     int dclass;        // 0: degrees exactly 6; 1: degrees 2..8
     int dv;            // every variable has this degree (0: mixed), resident form
-    bool lds_slots;    // slots in LDS (else global scratch)
+    int slot_mode;     // 0 global float slots, 1 LDS float slots, 2 LDS fixed-point accumulators
     bool half;         // fp16 state storage (streamed only)
     int threads;       // workgroup size
     int grid;          // workgroups

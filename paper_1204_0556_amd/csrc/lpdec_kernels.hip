@@ -247,14 +247,31 @@ __device__ __forceinline__ float x_update(const float *slots, const VarLoc &L, f
     return clamp01((s - gmu) * L.inv);
 }
 
-// one check update of degree D on registers z,u (length DMAX arrays)
-template <int D>
+// Exact, order-independent per-variable sums for codes whose slot array does not
+// fit in LDS: each replica difference w is converted to signed 32.32 fixed point
+// (exact for 2^-9 <= |w| < 2^31; smaller magnitudes are rounded down to a multiple
+// of 2^-32; larger ones saturate) and accumulated with 64-bit integer LDS atomics.  Integer addition is
+// associative, so the sum does not depend on the order the lanes arrive in.
+__device__ __forceinline__ unsigned long long to_fixed(float w) {
+    const double d = fmin(fmax((double)w, -2147483648.0), 2147483647.0);  // saturate to the range
+    const double hi = floor(d);
+    const double lo = (d - hi) * 4294967296.0;  // fraction, in [0, 2^32)
+    return ((unsigned long long)(unsigned)(int)hi << 32) | (unsigned long long)(unsigned)lo;
+}
+__device__ __forceinline__ float from_fixed(unsigned long long a) {
+    const double d = (double)(int)(unsigned)(a >> 32) * 4294967296.0 + (double)(unsigned)a;
+    return (float)(d * (1.0 / 4294967296.0));
+}
+
+// one check update of degree D on registers z,u (length DMAX arrays); x is read
+// from xs with stride XS (2 when x shares an accumulator entry)
+template <int D, int XS = 1>
 __device__ __forceinline__ void check_update(float *z, float *u, const uint32_t *meta, const float *xs,
                                              float rho, float &rp, float &rd) {
     float v[D], zn[D], xv[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        xv[k] = xs[meta[k] & 0xffffu];
+        xv[k] = xs[XS * (meta[k] & 0xffffu)];
         v[k] = fmaf(rho, xv[k] - z[k], z[k]) + u[k];  // q + u with q = rho x + (1-rho) z
     }
     project_pp<D>(v, zn);
@@ -287,13 +304,17 @@ __device__ __forceinline__ void st_state(void *p, size_t i, float a) {
 // check l of each of them.  CPT > 0 keeps those chunks' z,u (and packed edge
 // metadata) in registers; CPT == 0 walks the chunks and re-reads state.
 // Variable side: thread t owns internal variables t, t + NT, ...
-template <int DMIN, int DMAX, int CPT, int VPT, bool RES, bool PERSIST, bool LDS_SLOTS, bool HALF, int MAXT,
-          int DV>
+template <int DMIN, int DMAX, int CPT, int VPT, bool RES, bool PERSIST, int SM, bool HALF, int MAXT, int DV>
 __global__ void __launch_bounds__(MAXT)
 k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateIO sio, StreamArgs sa,
          int lds_E, int slot_stride, int state_stride) {
-    static_assert(!RES || (CPT > 0 && PERSIST && LDS_SLOTS), "register-resident form needs CPT>0");
-    extern __shared__ float lds[];
+    // SM: where the slot exchange lives -- 0 global float slots, 1 LDS float slots,
+    // 2 LDS fixed-point accumulators (x then sits in each entry's high word)
+    static_assert(!RES || (CPT > 0 && PERSIST && SM == 1), "register-resident form needs CPT>0");
+    static_assert(SM != 2 || CPT == 0, "accumulator mode walks chunks");
+    constexpr bool LDS_SLOTS = SM == 1;
+    constexpr int XS = (SM == 2) ? 2 : 1;
+    extern __shared__ __attribute__((aligned(16))) float lds[];  // 64-bit accumulators need 8-byte alignment
     __shared__ float s_red[2][2][kMaxWaves];
     __shared__ int s_frame;
 
@@ -304,7 +325,9 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
     const int NW = NT >> 6;
 
     float *slots = LDS_SLOTS ? lds : (sa.gslots + (size_t)blockIdx.x * slot_stride);
-    float *xs = LDS_SLOTS ? (lds + lds_E) : lds;
+    float *xs = (SM == 1) ? (lds + lds_E) : ((SM == 2) ? lds + 1 : lds);
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(lds);
+    unsigned *xprev = sa.gxprev ? sa.gxprev + (size_t)blockIdx.x * sa.gmu_stride : nullptr;
 
     constexpr int NC = CPT > 0 ? CPT : 1;
     float z[NC][DMAX], u[NC][DMAX];
@@ -336,6 +359,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         const int64_t loff = fb.llr_off ? fb.llr_off[f] : (int64_t)f * C.n;
         const float *gam = fb.llr + loff;
         const float thr = ip.tol2 * (float)C.E;
+        float *gmu_row = sa.gmu ? sa.gmu + (size_t)(PERSIST ? blockIdx.x : f) * sa.gmu_stride : nullptr;
 
         int iter0 = 0;
         if constexpr (!PERSIST) {
@@ -388,6 +412,8 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             }
         } else if constexpr (PERSIST) {
             for (int i = tid; i < C.n; i += NT) bad |= !finite_bits(gam[i]);
+            if (!C.var_identity)
+                for (int i = tid; i < C.n; i += NT) gmu_row[i] = gam[C.var_orig[i]] * ip.mu_inv;
         }
         if constexpr (PERSIST) {
             if (__syncthreads_or(bad)) {
@@ -453,6 +479,14 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             }
         }
 
+        if constexpr (SM == 2) {  // fresh accumulators (and previous x) for this frame
+            for (int i = tid; i < C.n; i += NT) {
+                acc[i] = 0ull;
+                if (xprev) xprev[i] = 0u;
+            }
+            __syncthreads();
+        }
+
         // -- phases ---------------------------------------------------------
         auto phase_a = [&]() {
             if constexpr (CPT > 0) {
@@ -478,7 +512,9 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                     if (lane < C.chunk_cnt[c]) {
                         for (int e = 0; e < d; ++e) {
                             const size_t p = off + e * kWave + lane;
-                            slots[C.edge_meta[p] >> 16] = ld_state<HALF>(gz, p) - ld_state<HALF>(gu, p);
+                            const float w = ld_state<HALF>(gz, p) - ld_state<HALF>(gu, p);
+                            if constexpr (SM == 2) atomicAdd(acc + (C.edge_meta[p] & 0xffffu), to_fixed(w));
+                            else slots[C.edge_meta[p] >> 16] = w;
                         }
                     }
                 }
@@ -504,10 +540,35 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                     const int i = tid + t * NT;
                     if (i < C.n) xs[i] = x_update(slots, VarLoc{vslot[t], vdeg[t], vinv[t]}, vg[t]);
                 }
-            } else {
+            } else if constexpr (SM == 2) {
+                const float *gsrc = C.var_identity ? gam : gmu_row;
+                const float gscale = C.var_identity ? ip.mu_inv : 1.0f;
                 for (int i = tid; i < C.n; i += NT) {
-                    const float g = gam[C.var_identity ? i : C.var_orig[i]] * ip.mu_inv;
-                    xs[i] = x_update(slots, var_loc(C, i), g);
+                    const unsigned prev = xprev ? xprev[i] : 0u;
+                    const unsigned long long a = acc[i] - ((unsigned long long)prev << 32);
+                    const float inv = (C.dv > 0) ? C.dv_inv : __int_as_float(C.var_info[i].y);
+                    const float x = clamp01((from_fixed(a) - gsrc[i] * gscale) * inv);
+                    acc[i] = (unsigned long long)__float_as_uint(x) << 32;
+                    if (xprev) xprev[i] = __float_as_uint(x);
+                }
+            } else {
+                // gamma/mu: straight from the frame's LLRs when variables keep their
+                // order, else from the copy staged in internal order
+                const float *gsrc = C.var_identity ? gam : gmu_row;
+                const float gscale = C.var_identity ? ip.mu_inv : 1.0f;
+                if (C.dv > 0) {  // kernel-uniform degree: a scalar loop
+                    for (int i = tid; i < C.n; i += NT) {
+                        const int b = C.dv * i;
+                        float acc = 0.0f;
+                        for (int p = 0; p < C.dv; ++p) acc += slots[b + p];
+                        xs[i] = clamp01((acc - gsrc[i] * gscale) * C.dv_inv);
+                    }
+                } else {
+                    for (int i = tid; i < C.n; i += NT) {
+                        const int2 vi = C.var_info[i];
+                        xs[i] = x_update(slots, VarLoc{vi.x & 0xffffff, vi.x >> 24, __int_as_float(vi.y)},
+                                         gsrc[i] * gscale);
+                    }
                 }
             }
         };
@@ -520,7 +581,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                     if (cval[k]) {
                         dispatch_degree<DMIN, DMAX>(cdeg[k], [&](auto dc) {
                             constexpr int D = decltype(dc)::value;
-                            check_update<D>(z[k], u[k], meta[k], xs, ip.rho, rp, rd);
+                            check_update<D, XS>(z[k], u[k], meta[k], xs, ip.rho, rp, rd);
                         });
                     }
                     if constexpr (!RES) {
@@ -550,7 +611,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                                 uu[e] = ld_state<HALF>(gu, p);
                                 mm[e] = C.edge_meta[p];
                             }
-                            check_update<D>(zz, uu, mm, xs, ip.rho, rp, rd);
+                            check_update<D, XS>(zz, uu, mm, xs, ip.rho, rp, rd);
 #pragma unroll
                             for (int e = 0; e < D; ++e) {
                                 const size_t p = off + e * kWave + lane;
@@ -593,8 +654,17 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 float rp = 0.0f, rd = 0.0f;
                 phase_c(rp, rd);
                 publish(it & 1, rp, rd);
+                // accumulator mode: the next phase A adds into the entries that
+                // phase C is still reading x from
+                if constexpr (SM == 2) __syncthreads();
             }
             iters = conv ? it - 1 : ip.max_iter;
+            if constexpr (SM == 2) {
+                // The stopping test ran after the next iteration's phase A, which
+                // accumulated into the entries holding x: restore the last x.
+                for (int i = tid; i < C.n; i += NT) acc[i] = (unsigned long long)xprev[i] << 32;
+                __syncthreads();
+            }
         } else {
             const int it = iter0 + 1;
             phase_a();
@@ -623,7 +693,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         const int64_t xoff = fb.x_off ? fb.x_off[f] : (int64_t)f * C.n;
         float frac = 0.0f;
         for (int i = tid; i < C.n; i += NT) {
-            const float x = xs[i];
+            const float x = xs[XS * i];
             fb.x_out[xoff + (C.var_identity ? i : C.var_orig[i])] = x;
             frac = fmaxf(frac, fminf(x, 1.0f - x));
         }
@@ -632,7 +702,8 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             const int d = C.chunk_deg[c], off = C.chunk_off[c];
             if (lane < C.chunk_cnt[c]) {
                 bool par = false;
-                for (int e = 0; e < d; ++e) par ^= (xs[C.edge_meta[off + e * kWave + lane] & 0xffffu] >= 0.5f);
+                for (int e = 0; e < d; ++e)
+                    par ^= (xs[XS * (C.edge_meta[off + e * kWave + lane] & 0xffffu)] >= 0.5f);
                 odd |= par;
             }
         }
@@ -687,7 +758,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
 // Streamed form set-up: zero (or load) each frame's state, flag invalid frames.
 template <bool HALF>
 __global__ void __launch_bounds__(256)
-k_stream_init(const DevCode *__restrict__ codes, FrameBatch fb, StateIO sio, StreamArgs sa) {
+k_stream_init(const DevCode *__restrict__ codes, FrameBatch fb, StateIO sio, StreamArgs sa, float mu_inv) {
     const int f = blockIdx.x;
     if (f >= fb.nframes) return;
     const int ci = fb.code_of_frame ? fb.code_of_frame[f] : 0;
@@ -707,6 +778,10 @@ k_stream_init(const DevCode *__restrict__ codes, FrameBatch fb, StateIO sio, Str
         st_state<HALF>(sa.z, base + p, z0);
         st_state<HALF>(sa.u, base + p, u0);
     }
+    if (sa.gmu && !C.var_identity) {
+        float *row = sa.gmu + (size_t)f * sa.gmu_stride;
+        for (int i = threadIdx.x; i < C.n; i += blockDim.x) row[i] = fb.llr[loff + C.var_orig[i]] * mu_inv;
+    }
     if (any_bad) {
         const int64_t xoff = fb.x_off ? fb.x_off[f] : (int64_t)f * C.n;
         for (int i = threadIdx.x; i < C.n; i += blockDim.x) fb.x_out[xoff + i] = 0.5f;
@@ -723,24 +798,26 @@ k_stream_init(const DevCode *__restrict__ codes, FrameBatch fb, StateIO sio, Str
 
 hipError_t launch_stream_init(const DevCode *codes_dev, int nframes, const LaunchConfig &cfg,
                               const FrameBatch &fb, const StateIO &sio, const StreamArgs &sa,
-                              const IterParams &, hipStream_t stream) {
+                              const IterParams &ip, hipStream_t stream) {
     if (nframes <= 0) return hipSuccess;
     if (cfg.half)
-        hipLaunchKernelGGL(k_stream_init<true>, dim3(nframes), dim3(256), 0, stream, codes_dev, fb, sio, sa);
+        hipLaunchKernelGGL(k_stream_init<true>, dim3(nframes), dim3(256), 0, stream, codes_dev, fb, sio, sa,
+                           ip.mu_inv);
     else
-        hipLaunchKernelGGL(k_stream_init<false>, dim3(nframes), dim3(256), 0, stream, codes_dev, fb, sio, sa);
+        hipLaunchKernelGGL(k_stream_init<false>, dim3(nframes), dim3(256), 0, stream, codes_dev, fb, sio, sa,
+                           ip.mu_inv);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Instantiation table.
 
-template <int DMIN, int DMAX, int CPT, int VPT, bool RES, bool PERSIST, bool LDS, bool HALF, int MAXT = kMaxThreads,
+template <int DMIN, int DMAX, int CPT, int VPT, bool RES, bool PERSIST, int SM, bool HALF, int MAXT = kMaxThreads,
           int DV = 0>
 static hipError_t go(const LaunchConfig &cfg, const DevCode *codes, const FrameBatch &fb, const IterParams &ip,
                      const StateIO &sio, const StreamArgs &sa, hipStream_t stream, int *occ) {
     if (cfg.threads > MAXT) return hipErrorInvalidConfiguration;
-    auto kern = k_decode<DMIN, DMAX, CPT, VPT, RES, PERSIST, LDS, HALF, MAXT, DV>;
+    auto kern = k_decode<DMIN, DMAX, CPT, VPT, RES, PERSIST, SM, HALF, MAXT, DV>;
     if (cfg.lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg.lds_bytes);
@@ -759,30 +836,28 @@ static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const 
 #define LPD_GO(...) return go<DMIN, DMAX, __VA_ARGS__>(cfg, codes, fb, ip, sio, sa, stream, occ)
     switch (cfg.form) {
         case Form::Resident:
-            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4 && cfg.dv == 3) LPD_GO(2, 4, true, true, true, false, 768, 3);
-            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8 && cfg.dv == 3) LPD_GO(2, 8, true, true, true, false, 768, 3);
-            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4) LPD_GO(2, 4, true, true, true, false, 768);
-            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8) LPD_GO(2, 8, true, true, true, false, 768);
+            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4 && cfg.dv == 3) LPD_GO(2, 4, true, true, 1, false, 768, 3);
+            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8 && cfg.dv == 3) LPD_GO(2, 8, true, true, 1, false, 768, 3);
+            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4) LPD_GO(2, 4, true, true, 1, false, 768);
+            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8) LPD_GO(2, 8, true, true, 1, false, 768);
             break;
         case Form::PersistentGlobal:
-            if (cfg.lds_slots) {
-                if (cfg.cpt_tmpl == 2) LPD_GO(2, 0, false, true, true, false);
-                if (cfg.cpt_tmpl == 0) LPD_GO(0, 0, false, true, true, false);
-            } else {
-                if (cfg.cpt_tmpl == 0) LPD_GO(0, 0, false, true, false, false);
-            }
-            break;
+            if (cfg.slot_mode == 1) LPD_GO(0, 0, false, true, 1, false);
+            if (cfg.slot_mode == 2) LPD_GO(0, 0, false, true, 2, false);
+            LPD_GO(0, 0, false, true, 0, false);
         case Form::Streamed:
-            if (cfg.lds_slots) {
-                if (cfg.cpt_tmpl == 2 && !cfg.half) LPD_GO(2, 0, false, false, true, false);
-                if (cfg.cpt_tmpl == 2 && cfg.half) LPD_GO(2, 0, false, false, true, true);
-                if (cfg.cpt_tmpl == 0 && !cfg.half) LPD_GO(0, 0, false, false, true, false);
-                if (cfg.cpt_tmpl == 0 && cfg.half) LPD_GO(0, 0, false, false, true, true);
-            } else {
-                if (!cfg.half) LPD_GO(0, 0, false, false, false, false);
-                LPD_GO(0, 0, false, false, false, true);
+            if (cfg.slot_mode == 1) {
+                if (cfg.cpt_tmpl == 2 && !cfg.half) LPD_GO(2, 0, false, false, 1, false);
+                if (cfg.cpt_tmpl == 2 && cfg.half) LPD_GO(2, 0, false, false, 1, true);
+                if (cfg.cpt_tmpl == 0 && !cfg.half) LPD_GO(0, 0, false, false, 1, false);
+                if (cfg.cpt_tmpl == 0 && cfg.half) LPD_GO(0, 0, false, false, 1, true);
             }
-            break;
+            if (cfg.slot_mode == 2) {
+                if (!cfg.half) LPD_GO(0, 0, false, false, 2, false);
+                LPD_GO(0, 0, false, false, 2, true);
+            }
+            if (!cfg.half) LPD_GO(0, 0, false, false, 0, false);
+            LPD_GO(0, 0, false, false, 0, true);
     }
 #undef LPD_GO
     return hipErrorInvalidValue;

@@ -43,13 +43,14 @@ struct Workspace {
     DevBuf queue;      // persistent work counter
     DevBuf codes;      // DevCode array (multi-code launches)
     DevBuf frame_meta; // code_of_frame / offsets
-    DevBuf z, u, st, active, gslots, gstate;
+    DevBuf z, u, st, active, gslots, gstate, gmu, gxprev;
     int *host_active = nullptr; // pinned
     char *host_meta = nullptr;  // pinned staging for per-call metadata
     size_t host_meta_bytes = 0;
     ~Workspace() {
         queue.release(); codes.release(); frame_meta.release();
         z.release(); u.release(); st.release(); active.release(); gslots.release(); gstate.release();
+        gmu.release(); gxprev.release();
         if (host_active) (void)hipHostFree(host_active);
         if (host_meta) (void)hipHostFree(host_meta);
         if (last) (void)hipEventDestroy(last);
