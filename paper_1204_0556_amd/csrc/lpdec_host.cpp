@@ -322,9 +322,16 @@ void streamed_config(const Shape &s, bool half, LaunchConfig *cfg) {
     cfg->form = Form::Streamed;
     cfg->slot_mode = slot_mode_for(s, &cfg->lds_bytes);
     cfg->cpt_tmpl = (cfg->slot_mode == 1 && s.cpt <= 2) ? 2 : 0;
-    cfg->vpt_tmpl = 0;
     cfg->dclass = s.dclass;
+    // register-held variable side (and its prefetch) when it fits: <= 8 per thread
+    const int vpt = (s.nmax + s.waves * kWave - 1) / (s.waves * kWave);
+    cfg->vpt_tmpl = 0;
     cfg->dv = 0;
+    // (measured slower than reading gamma in phase B, so kept off)
+    if (false && cfg->cpt_tmpl == 2 && vpt <= 8 && s.waves * kWave <= 768) {
+        cfg->dv = (s.dv == 3 && vpt <= 4) ? 3 : 0;
+        cfg->vpt_tmpl = cfg->dv == 3 ? 4 : 8;
+    }
     cfg->half = half;
     cfg->threads = s.waves * kWave;
     cfg->lds_E = s.Emax;
@@ -540,6 +547,7 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
         while (issued < p.max_iter) {
             const int cnt = std::min(block, p.max_iter - issued);
             for (int k = 0; k < cnt; ++k) {
+                ip.launch = issued + k;
                 hipError_t e = launch_fill_i32(sa.active_count, 0, 1, stream);
                 if (e == hipSuccess) e = launch_decode(cfg, codes_dev, fb, ip, sio, sa, stream);
                 if (e != hipSuccess) {

@@ -68,6 +68,7 @@ struct IterParams {
     float rho;
     float tol2;     // tol^2 (threshold = tol^2 * E)
     int max_iter;
+    int launch;     // streamed form: iterations already run by every unfinished frame
 };
 
 // Optional state input/output in CSR edge order ([frame][E]).

@@ -212,6 +212,20 @@ __device__ __forceinline__ float wave_sum(float x) {
     return (r0 + r1) + (r2 + r3);
 }
 
+// Workgroup barrier.  With LDS_ONLY the release/acquire fences cover LDS only, so
+// global loads still in flight (prefetched state) do not have to land first; the
+// phases exchange data through LDS alone in every form but the global-slot one.
+template <bool LDS_ONLY>
+__device__ __forceinline__ void wg_barrier() {
+    if constexpr (LDS_ONLY) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    } else {
+        __syncthreads();
+    }
+}
+
 template <int DMIN, int DMAX, typename F>
 __device__ __forceinline__ void dispatch_degree(int d, F &&f) {
     if constexpr (DMIN == DMAX) {
@@ -331,6 +345,13 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
 
     constexpr int NC = CPT > 0 ? CPT : 1;
     float z[NC][DMAX], u[NC][DMAX];
+    // streamed form: the next unfinished frame's state, loaded during phase C
+    constexpr bool PREFETCH = !PERSIST && CPT > 0;
+    constexpr int NP = PREFETCH ? NC : 1;
+    float pz[NP][DMAX], pu[NP][DMAX];
+    float pg[PREFETCH && VPT > 0 ? VPT : 1];  // gamma/mu of the prefetched frame
+    int pf_f = -1;
+    constexpr bool LBAR = SM != 0;  // phase barriers need only order LDS
     uint32_t meta[NC][DMAX];
     int cdeg[NC], coff[NC];
     bool cval[NC];
@@ -340,7 +361,26 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
     float vinv[VPT > 0 ? VPT : 1];
     int cur_code = -1;
 
-    int next_f = blockIdx.x;
+    // Streamed form: this workgroup owns frames blockIdx.x + k*G (G = gridDim.x).
+    // Their done-flags are read 64 at a time (one per lane) and the unfinished
+    // ones taken from a ballot mask, identical in every wave.
+    int sbase = (int)blockIdx.x - kWave * (int)gridDim.x;
+    unsigned long long smask = 0ull;
+    auto next_active = [&]() -> int {
+        for (;;) {
+            if (smask) {
+                const int j = __builtin_ctzll(smask);
+                smask &= smask - 1ull;
+                return sbase + j * (int)gridDim.x;
+            }
+            sbase += kWave * (int)gridDim.x;
+            if (sbase >= fb.nframes) return fb.nframes;
+            const int fj = sbase + lane * (int)gridDim.x;
+            const bool act = fj < fb.nframes && !sa.st[fj].done;
+            smask = __ballot(act);
+        }
+    };
+    int pending = -1;  // next frame, when already chosen (and prefetched)
     for (;;) {
         int f;
         if constexpr (PERSIST) {
@@ -349,8 +389,8 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             f = s_frame;
             __syncthreads();
         } else {
-            f = next_f;
-            next_f += gridDim.x;
+            f = pending >= 0 ? pending : next_active();
+            pending = -1;
         }
         if (f >= fb.nframes) break;
 
@@ -361,12 +401,8 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         const float thr = ip.tol2 * (float)C.E;
         float *gmu_row = sa.gmu ? sa.gmu + (size_t)(PERSIST ? blockIdx.x : f) * sa.gmu_stride : nullptr;
 
-        int iter0 = 0;
-        if constexpr (!PERSIST) {
-            const StreamFrame st = sa.st[f];
-            if (st.done) continue;
-            iter0 = st.iter;
-        }
+        // streamed form: unfinished frames advance in lockstep, one iteration per launch
+        const int iter0 = PERSIST ? 0 : ip.launch;
 
         // -- per-code register metadata -------------------------------------
         if constexpr (CPT > 0) {
@@ -400,8 +436,15 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         // -- frame set-up: gamma/mu, invalid-input check ----------------------
         bool bad = false;
         if constexpr (VPT > 0) {
+            const bool have = PREFETCH && pf_f == f;
 #pragma unroll
             for (int t = 0; t < VPT; ++t) {
+                if constexpr (PREFETCH && VPT > 0) {
+                    if (have) {
+                        vg[t] = pg[t];
+                        continue;
+                    }
+                }
                 const int i = tid + t * NT;
                 float g = 0.0f;
                 if (i < C.n) {
@@ -484,7 +527,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 acc[i] = 0ull;
                 if (xprev) xprev[i] = 0u;
             }
-            __syncthreads();
+            wg_barrier<LBAR>();
         }
 
         // -- phases ---------------------------------------------------------
@@ -493,9 +536,17 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
                     if constexpr (!RES) {
+                        const bool have = PREFETCH && pf_f == f;
 #pragma unroll
                         for (int e = 0; e < DMAX; ++e) {
                             if (cval[k] && e < cdeg[k]) {
+                                if constexpr (PREFETCH) {
+                                    if (have) {
+                                        z[k][e] = pz[k][e];
+                                        u[k][e] = pu[k][e];
+                                        continue;
+                                    }
+                                }
                                 const size_t p = coff[k] + e * kWave + lane;
                                 z[k][e] = ld_state<HALF>(gz, p);
                                 u[k][e] = ld_state<HALF>(gu, p);
@@ -644,19 +695,19 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             int it = 1;
             for (;; ++it) {
                 phase_a();
-                __syncthreads();
+                wg_barrier<LBAR>();
                 if (it > 1) {
                     if (converged((it - 1) & 1)) { conv = true; break; }
                     if (it > ip.max_iter) break;
                 }
                 phase_b();
-                __syncthreads();
+                wg_barrier<LBAR>();
                 float rp = 0.0f, rd = 0.0f;
                 phase_c(rp, rd);
                 publish(it & 1, rp, rd);
                 // accumulator mode: the next phase A adds into the entries that
                 // phase C is still reading x from
-                if constexpr (SM == 2) __syncthreads();
+                if constexpr (SM == 2) wg_barrier<LBAR>();
             }
             iters = conv ? it - 1 : ip.max_iter;
             if constexpr (SM == 2) {
@@ -668,13 +719,41 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         } else {
             const int it = iter0 + 1;
             phase_a();
-            __syncthreads();
+            wg_barrier<LBAR>();
             phase_b();
-            __syncthreads();
+            wg_barrier<LBAR>();
+            if constexpr (PREFETCH) {
+                // next unfinished frame of this workgroup; its state streams in while
+                // phase C computes (the LDS-only barriers do not wait for it)
+                const int g = next_active();
+                pending = g;
+                pf_f = -1;
+                if (g < fb.nframes) {
+                    if constexpr (VPT > 0) {
+                        const float *gg = fb.llr + (int64_t)g * C.n;
+#pragma unroll
+                        for (int t = 0; t < VPT; ++t) {
+                            const int i = tid + t * NT;
+                            pg[t] = (i < C.n) ? gg[C.var_identity ? i : C.var_orig[i]] * ip.mu_inv : 0.0f;
+                        }
+                    }
+                    const size_t gb = (size_t)g * C.E_int;
+#pragma unroll
+                    for (int k = 0; k < CPT; ++k)
+#pragma unroll
+                        for (int e = 0; e < DMAX; ++e)
+                            if (cval[k] && e < cdeg[k]) {
+                                const size_t p = gb + coff[k] + e * kWave + lane;
+                                pz[k][e] = ld_state<HALF>(sa.z, p);
+                                pu[k][e] = ld_state<HALF>(sa.u, p);
+                            }
+                    pf_f = g;
+                }
+            }
             float rp = 0.0f, rd = 0.0f;
             phase_c(rp, rd);
             publish(0, rp, rd);
-            __syncthreads();
+            wg_barrier<LBAR>();
             conv = converged(0);
             iters = it;
             const bool fin = conv || it >= ip.max_iter;
@@ -684,7 +763,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 else atomicAdd(sa.active_count, 1);
             }
             if (!fin) {
-                __syncthreads();  // LDS reuse by the next frame of this workgroup
+                wg_barrier<LBAR>();  // LDS reuse by the next frame of this workgroup
                 continue;
             }
         }
@@ -847,6 +926,12 @@ static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const 
             LPD_GO(0, 0, false, true, 0, false);
         case Form::Streamed:
             if (cfg.slot_mode == 1) {
+                if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4 && cfg.dv == 3 && !cfg.half)
+                    LPD_GO(2, 4, false, false, 1, false, 768, 3);
+                if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4 && cfg.dv == 3 && cfg.half)
+                    LPD_GO(2, 4, false, false, 1, true, 768, 3);
+                if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8 && !cfg.half) LPD_GO(2, 8, false, false, 1, false, 768);
+                if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8 && cfg.half) LPD_GO(2, 8, false, false, 1, true, 768);
                 if (cfg.cpt_tmpl == 2 && !cfg.half) LPD_GO(2, 0, false, false, 1, false);
                 if (cfg.cpt_tmpl == 2 && cfg.half) LPD_GO(2, 0, false, false, 1, true);
                 if (cfg.cpt_tmpl == 0 && !cfg.half) LPD_GO(0, 0, false, false, 1, false);
