@@ -11,6 +11,8 @@ Functions
   project_info(v)       the same plus (r, beta_opt, branch).
   max_linear(c)         Algorithm 3 (Appendix A): argmax c^T z over PP_d.
   decode(H, llr, ...)   Algorithm 1 with over-relaxation (Sec. 3.3, Sec. 5.2).
+  dual_decode(H, llr, ...)  dual subgradient ascent with Algorithm 3 (Appendix A).
+  evaluate(H, llr, x, sent)  word/bit errors and the ML lower-bound test (Sec. 5.1).
 """
 from __future__ import annotations
 
@@ -26,6 +28,7 @@ _LIB = os.path.join(_HERE, "liblpdec_oracle.so")
 
 BRANCH_ALL_ONE, BRANCH_BOX, BRANCH_SEARCH = 0, 1, 2
 FLAG_CONVERGED, FLAG_INTEGRAL, FLAG_CODEWORD, FLAG_CERTIFIED, FLAG_INVALID = 0x01, 0x02, 0x04, 0x08, 0x80
+EVAL_WORD_ERROR, EVAL_CODEWORD, EVAL_ML_ERROR = 0x01, 0x02, 0x04
 
 
 def build(force: bool = True) -> str:
@@ -59,6 +62,15 @@ def _load():
             P(ctypes.c_ubyte), P(ctypes.c_double), P(ctypes.c_double), ctypes.c_int, ctypes.c_int,
             P(ctypes.c_longlong)]
         lib.lpo_decode_batch.restype = ctypes.c_int
+        lib.lpo_dual_decode_batch.argtypes = [
+            ctypes.c_int, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), ctypes.c_int, P(ctypes.c_float),
+            ctypes.c_double, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_int), P(ctypes.c_ubyte)]
+        lib.lpo_dual_decode_batch.restype = ctypes.c_int
+        lib.lpo_evaluate.argtypes = [
+            ctypes.c_int, ctypes.c_int, P(ctypes.c_int), P(ctypes.c_int), ctypes.c_int, P(ctypes.c_float),
+            P(ctypes.c_double), P(ctypes.c_ubyte), P(ctypes.c_int), P(ctypes.c_double), P(ctypes.c_double),
+            P(ctypes.c_ubyte)]
+        lib.lpo_evaluate.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -141,3 +153,52 @@ def decode(H, llr, mu=3.0, rho=1.9, max_iter=1000, tol=1e-5, state=False, z0=Non
     if rc != 0:
         raise ValueError(f"oracle decode failed ({rc})")
     return Result(x, it, fl, z, u, counts)
+
+
+def dual_decode(H, llr, mu=3.0, max_iter=1000) -> Result:
+    """Dual subgradient ascent (Appendix A) on frames of one code; mu is the step size."""
+    lib = _load()
+    llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float32)
+    B, n = llr.shape
+    if n != H.n:
+        raise ValueError("llr width != code length")
+    rp = np.ascontiguousarray(H.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(H.col_idx, dtype=np.int32)
+    x = np.empty((B, n), np.float64)
+    it = np.empty(B, np.int32)
+    fl = np.empty(B, np.uint8)
+    rc = lib.lpo_dual_decode_batch(H.m, n, _ptr(rp, ctypes.c_int), _ptr(ci, ctypes.c_int), B,
+                                   _ptr(llr, ctypes.c_float), float(mu), int(max_iter),
+                                   _ptr(x, ctypes.c_double), _ptr(it, ctypes.c_int), _ptr(fl, ctypes.c_ubyte))
+    if rc != 0:
+        raise ValueError(f"lpo_dual_decode_batch failed ({rc})")
+    return Result(x, it, fl)
+
+
+def evaluate(H, llr, x, sent=None) -> dict:
+    """Per-frame bit errors, costs gamma^T xhat and gamma^T sent (FP64), and outcome
+    bits (EVAL_WORD_ERROR, EVAL_CODEWORD, EVAL_ML_ERROR); sent=None is all-zero."""
+    lib = _load()
+    llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float32)
+    B, n = llr.shape
+    x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.float64)
+    if x.shape != (B, n) or n != H.n:
+        raise ValueError("llr and x must be [frames, n]")
+    sp = None
+    if sent is not None:
+        sent = np.ascontiguousarray(np.atleast_2d(sent), dtype=np.uint8)
+        if sent.shape != (B, n):
+            raise ValueError("sent must be [frames, n]")
+        sp = _ptr(sent, ctypes.c_ubyte)
+    rp = np.ascontiguousarray(H.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(H.col_idx, dtype=np.int32)
+    be = np.empty(B, np.int32)
+    ch = np.empty(B, np.float64)
+    cs = np.empty(B, np.float64)
+    oc = np.empty(B, np.uint8)
+    rc = lib.lpo_evaluate(H.m, n, _ptr(rp, ctypes.c_int), _ptr(ci, ctypes.c_int), B, _ptr(llr, ctypes.c_float),
+                          _ptr(x, ctypes.c_double), sp, _ptr(be, ctypes.c_int), _ptr(ch, ctypes.c_double),
+                          _ptr(cs, ctypes.c_double), _ptr(oc, ctypes.c_ubyte))
+    if rc != 0:
+        raise ValueError(f"lpo_evaluate failed ({rc})")
+    return {"bit_errors": be, "cost_hat": ch, "cost_sent": cs, "outcome": oc}

@@ -22,6 +22,11 @@
  *   lpo_max_linear   Algorithm 3 (Appendix A): maximise c^T z over PP_d.
  *   lpo_decode_batch Algorithm 1 (Sec. 3.3) with the over-relaxation of Sec. 5.2
  *                    (Boyd et al., Sec. 3.4.3), one frame per worker thread.
+ *   lpo_dual_decode_batch  the dual subgradient ascent of Appendix A: x by the
+ *                    Heaviside rule, z_j by Algorithm 3, lambda_j += mu (P_j x - z_j).
+ *   lpo_evaluate     the per-frame bookkeeping behind the ML lower bound of
+ *                    Sec. 5.1: word error, codeword test of the rounded estimate,
+ *                    and whether its cost beats the transmitted codeword's.
  *
  * Readings of the paper taken here (each listed in the design notes):
  *   - Over-relaxation: q_j = rho P_j x + (1 - rho) z_j replaces P_j x in both the
@@ -381,4 +386,145 @@ int lpo_decode_batch(int m, int n, const int *row_ptr, const int *col_idx, int b
         for (int b = 0; b < 3; ++b) proj_counts[b] = J.n_proj[b];
     graph_free(&g);
     return J.error ? -2 : 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Dual subgradient ascent (Appendix A), one frame.                           */
+/*
+ * With the un-augmented Lagrangian L0 = gamma^T x + sum_j lambda_j^T (P_j x - z_j):
+ *   x^{k+1}_i = theta(-gamma_i - sum_{j in N_v(i)} lambda_{j,i})   theta(t) = [t > 0]
+ *   z_j^{k+1} = argmax_{z in PP_d} lambda_j^T z                    (Algorithm 3)
+ *   lambda_j^{k+1} = lambda_j + mu (P_j x^{k+1} - z_j^{k+1})
+ * x and z both use lambda^k.  Each update adds mu times an integer in {-1,0,1}
+ * to an edge's multiplier, so lambda_e = mu K_e with an integer count K_e; the
+ * counts are carried exactly and lambda is formed from them (reading: this is
+ * the same iteration without accumulated rounding).  The decision for x_i is
+ * taken in FP64 as (-gamma_i) - mu S_i with S_i the integer sum of its counts.
+ * Stopping (reading; the appendix gives none): when P_j x = z_j for every
+ * check, lambda no longer moves and (x, z) minimises L0 while being feasible,
+ * so x is an LP optimum and a codeword: the frame is converged and certified.
+ * Otherwise the iteration stops after max_iter passes and returns the last x.
+ */
+static void dual_frame(const lpo_graph *g, double mu, int max_iter, const double *gamma, long long *K,
+                       double *x, int *iters, unsigned char *flags) {
+    const int n = g->n, m = g->m;
+    for (int i = 0; i < n; ++i) {
+        if (!isfinite(gamma[i])) {
+            for (int k = 0; k < n; ++k) x[k] = 0.5;
+            *iters = 0;
+            *flags = LPO_FLAG_INVALID;
+            return;
+        }
+    }
+    double c[LPO_MAXD], zv[LPO_MAXD];
+    int converged = 0, k;
+    for (k = 1; k <= max_iter; ++k) {
+        for (int i = 0; i < n; ++i) {
+            long long S = 0;
+            for (int t = g->var_ptr[i]; t < g->var_ptr[i + 1]; ++t) S += K[g->var_edge[t]];
+            const double t_i = (-gamma[i]) - mu * (double)S;
+            x[i] = t_i > 0.0 ? 1.0 : 0.0;
+        }
+        int moved = 0;
+        for (int j = 0; j < m; ++j) {
+            const int e0 = g->row_ptr[j], d = g->row_ptr[j + 1] - e0;
+            for (int t = 0; t < d; ++t) c[t] = mu * (double)K[e0 + t];
+            lpo_max_linear(d, c, zv);
+            for (int t = 0; t < d; ++t) {
+                const long long delta = (long long)x[g->col_idx[e0 + t]] - (long long)zv[t];
+                if (delta != 0) moved = 1;
+                K[e0 + t] += delta;
+            }
+        }
+        if (!moved) { converged = 1; break; }
+    }
+    *iters = converged ? k : max_iter;
+    unsigned char fl = LPO_FLAG_INTEGRAL | (converged ? LPO_FLAG_CONVERGED : 0);
+    int ok = 1;
+    for (int j = 0; j < m && ok; ++j) {
+        int par = 0;
+        for (int e = g->row_ptr[j]; e < g->row_ptr[j + 1]; ++e) par ^= (x[g->col_idx[e]] >= 0.5);
+        if (par) ok = 0;
+    }
+    if (ok) fl |= LPO_FLAG_CODEWORD;
+    if ((fl & 0x07) == 0x07) fl |= LPO_FLAG_CERTIFIED;
+    *flags = fl;
+}
+
+/* Decode `batch` frames of one code by dual subgradient ascent (Appendix A).
+ * llr [batch][n] float; mu > 0 is the step size; x_out [batch][n] receives the
+ * final x (0 or 1); iters_out, flags_out [batch].  Frames run one after another.
+ * Returns 0, -1 on bad input, -2 on allocation failure. */
+int lpo_dual_decode_batch(int m, int n, const int *row_ptr, const int *col_idx, int batch, const float *llr,
+                          double mu, int max_iter, double *x_out, int *iters_out, unsigned char *flags_out) {
+    if (m < 1 || n < 1 || batch < 0 || max_iter < 1 || !(mu > 0.0)) return -1;
+    for (int j = 0; j < m; ++j) {
+        int d = row_ptr[j + 1] - row_ptr[j];
+        if (d < 1 || d > LPO_MAXD) return -1;
+        for (int e = row_ptr[j]; e < row_ptr[j + 1]; ++e)
+            if (col_idx[e] < 0 || col_idx[e] >= n) return -1;
+    }
+    lpo_graph g;
+    if (graph_build(&g, m, n, row_ptr, col_idx)) { graph_free(&g); return -2; }
+    for (int i = 0; i < n; ++i)
+        if (g.var_ptr[i + 1] == g.var_ptr[i]) { graph_free(&g); return -1; }
+    double *gamma = (double *)malloc(sizeof(double) * (size_t)n);
+    long long *K = (long long *)malloc(sizeof(long long) * (size_t)g.nnz);
+    if (!gamma || !K) { free(gamma); free(K); graph_free(&g); return -2; }
+    for (int f = 0; f < batch; ++f) {
+        for (int i = 0; i < n; ++i) gamma[i] = (double)llr[(size_t)f * n + i];
+        memset(K, 0, sizeof(long long) * (size_t)g.nnz);
+        dual_frame(&g, mu, max_iter, gamma, K, x_out + (size_t)f * n, &iters_out[f], &flags_out[f]);
+    }
+    free(gamma); free(K);
+    graph_free(&g);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* ML lower-bound bookkeeping (Sec. 5.1, the MacKay-code experiment).          */
+/*
+ * The decoder's x is rounded to xhat_i = [x_i >= 1/2].  A frame is a word error
+ * when xhat differs from the transmitted word.  If xhat is nevertheless a
+ * codeword (H xhat = 0) and it is more likely than the transmitted word given
+ * the channel output -- cost gamma^T xhat < gamma^T sent, since gamma is the
+ * negative log-likelihood ratio (Sec. 2) -- an ML decoder would have erred as
+ * well.  Counting only those frames gives a lower bound on the ML word-error
+ * rate.  Costs are summed in FP64; a tie counts as an ML success.
+ *   sent   [batch][n] bits, or NULL for the all-zero codeword
+ *   outcome bit0 word error, bit1 xhat is a codeword, bit2 ML error witnessed
+ */
+int lpo_evaluate(int m, int n, const int *row_ptr, const int *col_idx, int batch, const float *llr,
+                 const double *x, const unsigned char *sent, int *bit_errors, double *cost_hat,
+                 double *cost_sent, unsigned char *outcome) {
+    if (m < 1 || n < 1 || batch < 0) return -1;
+    for (int f = 0; f < batch; ++f) {
+        const float *g = llr + (size_t)f * n;
+        const double *xf = x + (size_t)f * n;
+        const unsigned char *sf = sent ? sent + (size_t)f * n : NULL;
+        int be = 0;
+        double ch = 0.0, cs = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const int xh = xf[i] >= 0.5;
+            const int si = sf ? (sf[i] != 0) : 0;
+            be += xh != si;
+            if (xh) ch += (double)g[i];
+            if (si) cs += (double)g[i];
+        }
+        int cw = 1;
+        for (int j = 0; j < m && cw; ++j) {
+            int par = 0;
+            for (int e = row_ptr[j]; e < row_ptr[j + 1]; ++e) par ^= (xf[col_idx[e]] >= 0.5);
+            if (par) cw = 0;
+        }
+        unsigned char o = 0;
+        if (be) o |= 0x01;
+        if (cw) o |= 0x02;
+        if (be && cw && ch < cs) o |= 0x04;
+        bit_errors[f] = be;
+        cost_hat[f] = ch;
+        cost_sent[f] = cs;
+        outcome[f] = o;
+    }
+    return 0;
 }

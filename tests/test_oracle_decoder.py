@@ -99,6 +99,19 @@ def test_fixed_point_is_the_lp_optimum(rho, seed):
         assert abs(obj - lp1) < 1e-6 * (1 + abs(lp1)), (f, obj, lp1, res.iters[f])
 
 
+def test_bsc_fixed_point_objective_is_the_lp_optimum():
+    # BSC costs take two values, so the LP optimum is often not unique (ties);
+    # what is unique is its value (Sec. 2, footnote on the BSC).
+    H = small_code(18, 9, 3, 8)
+    rng = np.random.default_rng(21)
+    gamma = W.bsc_llr(H.n, 6, 0.15, rng)
+    res = oracle.decode(H, gamma, mu=3.0, rho=1.9, max_iter=20000, tol=1e-10)
+    for f in range(gamma.shape[0]):
+        g = gamma[f].astype(np.float64)
+        lp, _ = pins.feldman_lp(H.row_ptr, H.col_idx, H.n, g)
+        assert abs(g @ res.x[f] - lp) < 1e-6 * (1 + abs(lp)), (f, g @ res.x[f], lp)
+
+
 def test_objective_gap_shrinks_with_iterations():
     # gamma^T xhat - gamma^T x* = O(M d mu / T) (Sec. 3.3): the gap at a fixed T falls
     # as T grows (tolerance 0 disables stopping).

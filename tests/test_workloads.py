@@ -72,3 +72,24 @@ def test_serving_trace_rates():
     assert 0.8 * 10000 < frames < 1.2 * 10000
     assert all(1 <= r.frames <= 256 for r in tr)
     assert all(np.diff([r.arrival_s for r in tr]) > 0)
+
+
+def test_bsc_ensemble():
+    codes = W.bsc_ensemble()
+    assert len(codes) == W.BSC_ENSEMBLE_SIZE == 100
+    names = set()
+    for H in codes[:10]:
+        assert (H.m, H.n, H.nnz) == (501, 1002, 3006)
+        assert set(H.check_degrees()) == {6} and set(H.var_degrees()) == {3}
+        # no parallel edges: every (check, variable) pair appears once
+        pairs = set(zip(np.repeat(np.arange(H.m), 6).tolist(), H.col_idx.tolist()))
+        assert len(pairs) == H.nnz
+        names.add(H.name)
+    assert len(names) == 10
+    # length-4 cycles are allowed (the paper removed parallel edges only)
+    assert sum(len(H.four_cycle_pairs()) for H in codes[:10]) > 0
+    a = W.bsc_batch(codes[0], 3, 0.05)
+    b = W.bsc_batch(codes[0], 3, 0.05)
+    c = W.bsc_batch(codes[1], 3, 0.05)
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    assert set(np.unique(a).tolist()) <= {np.float32(np.log(0.95 / 0.05)), np.float32(-np.log(0.95 / 0.05))}

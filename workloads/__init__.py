@@ -14,14 +14,15 @@ import functools
 import numpy as np
 
 from .channel import awgn_llr, bsc_llr, sigma2_for
-from .codes import (ParityCheckMatrix, gallager_regular, gf2_rank, irregular, rng_for,
-                    single_check)
+from .codes import (ParityCheckMatrix, gallager_regular, gf2_rank, irregular, random_regular,
+                    rng_for, single_check)
 
 __all__ = [
     "ParityCheckMatrix", "gallager_regular", "irregular", "single_check", "gf2_rank", "rng_for",
     "awgn_llr", "bsc_llr", "sigma2_for", "PAPER_PARAMS", "gallager36", "gallager48",
     "irregular_half", "IRREGULAR_LENGTHS", "Batch", "awgn_batch", "mixed_batch",
-    "HEADLINE_SNRS", "serving_trace", "SERVING_LENGTHS",
+    "HEADLINE_SNRS", "serving_trace", "SERVING_LENGTHS", "random_regular", "bsc_ensemble",
+    "bsc_batch", "BSC_CROSSOVERS", "BSC_ENSEMBLE_SIZE",
 ]
 
 # Decoder parameters used for every simulation of Sec. 5.1: eps = 1e-5, mu = 3,
@@ -29,6 +30,11 @@ __all__ = [
 PAPER_PARAMS = dict(mu=3.0, rho=1.9, max_iter=1000, tol=1e-5)
 
 HEADLINE_SNRS = (1.5, 2.0, 2.5, 3.0)
+# BSC crossover probabilities for the random-code ensemble (the paper plots its
+# BSC results against crossover without printing the grid; this one spans the
+# LP decoder's waterfall for (3,6) codes of length 1002).
+BSC_CROSSOVERS = (0.03, 0.04, 0.05, 0.06, 0.07)
+BSC_ENSEMBLE_SIZE = 100
 IRREGULAR_LENGTHS = (576, 1152, 2304, 4608, 6912, 8064)
 SERVING_LENGTHS = (96, 576, 2640, 8064, 16384)
 
@@ -53,6 +59,14 @@ def irregular_half(n: int) -> ParityCheckMatrix:
     """Rate-1/2 irregular code: variable degrees {2:1/4, 3:1/2, 6:1/4}, check degrees
     {6,7,8} one third each, m = n/2, nnz = 3.5 n."""
     return irregular(n, {2: 0.25, 3: 0.5, 6: 0.25}, {6: 1 / 3, 7: 1 / 3, 8: 1 / 3}, m=n // 2, seed=n)
+
+
+@functools.lru_cache(maxsize=None)
+def bsc_ensemble(n: int = 1002, count: int = BSC_ENSEMBLE_SIZE) -> tuple:
+    """`count` random (3,6)-regular codes of length n without parallel edges (length-4
+    cycles allowed), seeds 0..count-1: the stand-in for the paper's ensemble of 100
+    random n = 1002 codes."""
+    return tuple(random_regular(n, 3, 6, seed=s) for s in range(count))
 
 
 @dataclasses.dataclass
@@ -80,6 +94,13 @@ def awgn_batch(H: ParityCheckMatrix, frames: int, ebn0_db: float, tag: str = "aw
     """[frames, n] float32 gamma for one code at one Eb/N0 (seeded by code length, SNR and block)."""
     rng = rng_for(tag, H.n, H.m, int(round(ebn0_db * 1000)), block)
     return awgn_llr(H.n, frames, ebn0_db, rng)
+
+
+def bsc_batch(H: ParityCheckMatrix, frames: int, p: float, tag: str = "bsc", block: int = 0) -> np.ndarray:
+    """[frames, n] float32 gamma = +-log((1-p)/p) for the all-zero codeword over a BSC(p),
+    seeded by the code (length, name), the crossover and a block index."""
+    rng = rng_for(tag, H.n, H.m, H.name, int(round(p * 1e6)), block)
+    return bsc_llr(H.n, frames, p, rng)
 
 
 def mixed_batch(codes, frames: int, snr_lo: float, snr_hi: float, tag: str = "mixed", seed: int = 0) -> Batch:

@@ -11,6 +11,9 @@ that the FP64 oracle and the HIP library are fed identical codes.
 * ``irregular`` -- a random socket matching for given variable / check degree
   distributions, with parallel edges and length-4 cycles repaired by swapping
   edge endpoints (degrees are preserved).
+* ``random_regular`` -- a (dv, dc)-regular socket matching drawn whole and
+  rejected while it has a parallel edge; length-4 cycles are kept.  This is how
+  the paper describes its ensemble of n = 1002 codes (Sec. 5.1).
 
 Row neighbourhoods are returned sorted, i_1 < i_2 < ... < i_d, which is the
 ordering the paper uses for the selection matrices P_j (Sec. 2).
@@ -158,6 +161,26 @@ def irregular(n: int, var_dist: dict, chk_dist: dict, m: int | None = None, seed
                 f = int(rng.integers(E))
                 cs[e], cs[f] = cs[f], cs[e]
     raise RuntimeError("could not build a 4-cycle-free irregular code")
+
+
+def random_regular(n: int, dv: int, dc: int, seed: int = 0, max_draws: int = 100000) -> ParityCheckMatrix:
+    """Random (dv, dc)-regular code: a uniform socket matching, re-drawn whole until
+    no variable meets the same check twice.  Length-4 cycles are allowed."""
+    if (n * dv) % dc:
+        raise ValueError("n * dv must be a multiple of dc")
+    m = n * dv // dc
+    E = n * dv
+    vs = np.repeat(np.arange(n), dv)
+    cs0 = np.repeat(np.arange(m), dc)
+    rng = rng_for("random_regular", n, dv, dc, seed)
+    for _ in range(max_draws):
+        cs = cs0[rng.permutation(E)]
+        # sockets of one variable are consecutive in vs: a parallel edge is a repeated
+        # check among a variable's dv sockets
+        per_var = np.sort(cs.reshape(n, dv), axis=1)
+        if not np.any(per_var[:, 1:] == per_var[:, :-1]):
+            return _from_edges(m, n, cs.copy(), vs.copy(), f"random({dv},{dc}) n={n} seed={seed}")
+    raise RuntimeError("no parallel-edge-free draw")
 
 
 def _degree_sequence(count: int, dist: dict) -> np.ndarray:
