@@ -57,6 +57,38 @@ def algorithmic_ops_per_frame_iter(H) -> int:
     return ops
 
 
+KERNEL_SOURCES = ("paper_1204_0556_amd/csrc/lpdec_kernels.hip", "paper_1204_0556_amd/csrc/lpdec_internal.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(name: str, field: str = "traffic_bytes_per_launch"):
+    """HBM bytes per launch of the decoder kernel from the committed counter summary
+    profiles/<name>.md (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration),
+    or None when the summary is missing or was taken from other kernel sources."""
+    path = os.path.join(ROOT, "profiles", name + ".md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if line.startswith("    ") and ":" in line:
+            k, v = line.strip().split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return int(fields[field])
+    except (KeyError, ValueError):
+        return None
+
+
 def run_serving(lp, W, seconds: float, seed: int = 0, budget_bytes: int = 512 << 20):
     """Replay a seeded Poisson trace in real time through the continuous-batching
     server: mean 50k frames/s, 1..256 frames per request, codes n in
@@ -342,13 +374,15 @@ def main():
     if form == "resident":
         achieved = ops * frame_iters / kernel_s / 1e9
         res["roofline"] = {"bound": "alu", "achieved": round(achieved / 1e3, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 2),
-                           "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_GOPS, 4), "traffic": None,
+                           "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_GOPS, 4),
+                           "traffic": profiled_traffic("k_decode_resident_n2640_headline"),
                            "kernel": "k_decode (resident)", "ops_per_frame_iter": ops,
                            "kernel_ms": round(gpu_ms, 3), "launches_per_step": 1}
     else:
         achieved = B * frame_iters / kernel_s / 1e9
         res["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                           "frac": round(achieved / HBM_PEAK_GBS, 4),
+                           "traffic": profiled_traffic(f"k_decode_{form}_n2640_headline"),
                            "kernel": f"k_decode ({form})", "bytes_per_frame_iter": B,
                            "kernel_ms": round(gpu_ms, 3)}
 
@@ -366,6 +400,9 @@ def main():
         sfi = int(sit.sum())
         sach = B * sfi / (sms / 1e3) / 1e9
         res["streamed"] = {"mbit_s": round(F * H.n / (sms / 1e3) / 1e6, 2), "ms": round(sms, 3),
+                           "algorithmic_bytes": B * sfi,
+                           "traffic_bytes": profiled_traffic("k_decode_streamed_n2640_headline",
+                                                             "traffic_bytes_per_decode"),
                            "launches": int(sit.max()), "hbm_achieved_gbs": round(sach, 1),
                            "hbm_frac": round(sach / HBM_PEAK_GBS, 4), "bytes_per_frame_iter": B}
         # plain: one frame per launch sequence (streamed form, batch of one), sampled

@@ -153,6 +153,99 @@ lpdec_status lpdec_decode_multi(const lpdec_code *const *codes, int32_t ncodes, 
                                 float *x_out, const int64_t *x_offset, int64_t x_len,
                                 int32_t *iters_out, uint8_t *flags_out, void *stream);
 
+/* ------------------------------------------------------------------------- */
+/* Dual subgradient ascent (Appendix A): the other decomposition the paper
+ * describes.  With the un-augmented Lagrangian, x_i = [-gamma_i - sum of the
+ * variable's multipliers > 0], each z_j maximises lambda_j^T z over PP_d
+ * (Algorithm 3, O(d)), and lambda_j += mu (P_j x - z_j) with constant step mu.
+ * Every multiplier is mu times an integer, so the iteration runs on integer
+ * counts; the x decision is taken in FP64.  A frame stops when P_j x = z_j for
+ * every check (lambda stops moving; x is then an LP optimum and a codeword:
+ * converged, integral, codeword and certified are all set) or after max_iter
+ * iterations.  x_out holds the last x (0 or 1 per bit).
+ *   p  host; uses mu (step size, > 0) and max_iter; NULL = defaults
+ * Other arguments as lpdec_decode.  LPDEC_EUNSUPPORTED when the code needs more
+ * than 8 check chunks per wave (m > 8192) or 9 n bytes exceed the LDS. */
+lpdec_status lpdec_decode_dual(const lpdec_code *code, int32_t batch, const float *llr,
+                               const lpdec_params *p, float *x_out, int32_t *iters_out,
+                               uint8_t *flags_out, void *stream);
+
+/* ML lower-bound bookkeeping (Sec. 5.1).  For each frame the estimate is
+ * rounded, xhat_i = [x_i >= 1/2], and compared with the transmitted word:
+ *   sent        device [batch*n] bytes (nonzero = 1), or NULL for the all-zero
+ *               codeword; indexed like x
+ *   bit_errors  device [batch] int32: |{i : xhat_i != sent_i}|
+ *   cost_hat    device [batch] FP64: gamma^T xhat
+ *   cost_sent   device [batch] FP64: gamma^T sent
+ *   outcome     device [batch] uint8: LPDEC_EVAL_* bits
+ * H xhat = 0 is recomputed from the code.  A word error whose estimate is a
+ * codeword cheaper than the transmitted one (gamma is the negative
+ * log-likelihood ratio, Sec. 2) would also be an ML decoding error; counting
+ * those frames gives a lower bound on the ML word-error rate.  A cost tie counts
+ * as an ML success.  Costs are summed in FP64 in a tree order. */
+#define LPDEC_EVAL_WORD_ERROR 0x01u
+#define LPDEC_EVAL_CODEWORD 0x02u
+#define LPDEC_EVAL_ML_ERROR 0x04u
+lpdec_status lpdec_evaluate(const lpdec_code *code, int32_t batch, const float *llr, const float *x,
+                            const uint8_t *sent, int32_t *bit_errors, double *cost_hat,
+                            double *cost_sent, uint8_t *outcome, void *stream);
+
+/* lpdec_evaluate over frames of several codes, laid out as for lpdec_decode_multi
+ * (host code_of_frame / llr_offset / x_offset, checked against llr_len / x_len;
+ * `sent` is indexed by x_offset). */
+lpdec_status lpdec_evaluate_multi(const lpdec_code *const *codes, int32_t ncodes, int32_t nframes,
+                                  const int32_t *code_of_frame, const int64_t *llr_offset,
+                                  const float *llr, int64_t llr_len, const float *x,
+                                  const int64_t *x_offset, int64_t x_len, const uint8_t *sent,
+                                  int32_t *bit_errors, double *cost_hat, double *cost_sent,
+                                  uint8_t *outcome, void *stream);
+
+/* ------------------------------------------------------------------------- */
+/* Launch shape and tuning.  Frames are independent and every sum inside a
+ * frame has a fixed order, so the launch shape changes speed only: results are
+ * bitwise the same for any workgroups-per-CU setting. */
+
+typedef struct {
+    int32_t mode;                  /* the form these figures describe (LPDEC_MODE_*)      */
+    int32_t threads;               /* workgroup size = threads per frame                  */
+    int32_t lds_bytes;             /* dynamic LDS per workgroup                           */
+    int32_t vgprs;                 /* vector registers per lane of the selected kernel    */
+    int32_t runtime_blocks_per_cu; /* the HIP runtime's occupancy estimate                */
+    int32_t resource_blocks_per_cu;/* workgroups per CU that registers and LDS allow      */
+    int32_t blocks_per_cu;         /* what decode launches of this code use now           */
+    int32_t register_chunks;       /* 64-check chunks whose z,u a wave keeps in registers
+                                      (0: re-read from memory in each phase)              */
+} lpdec_launch_info;
+
+/* The launch a decode of `code` with parameters `p` (NULL = defaults; mode and
+ * storage matter) would use.  Errors as lpdec_decode's mode resolution. */
+lpdec_status lpdec_code_launch_info(const lpdec_code *code, const lpdec_params *p,
+                                    lpdec_launch_info *out);
+
+/* Fix the launch of one form (LPDEC_MODE_RESIDENT, _STREAMED or
+ * _PERSISTENT_GLOBAL) for this code.
+ *   blocks_per_cu    workgroups per CU, 1..32; 0 restores the runtime's estimate
+ *   register_chunks  streamed form only: 0 re-reads each chunk's z,u in every
+ *                    phase, 2 keeps them in registers (when the code allows);
+ *                    -1 restores the default.  Ignored by the other forms.
+ * Not synchronised with decodes running on other threads. */
+lpdec_status lpdec_code_set_tuning(lpdec_code *code, int32_t mode, int32_t blocks_per_cu,
+                                   int32_t register_chunks);
+
+/* Autotuner: decode the caller's sample batch (device llr [batch*n]) with
+ * parameters `p` once per candidate launch -- workgroups per CU 1..max_blocks_per_cu,
+ * times register_chunks {default, 0} for the streamed form -- after one untimed
+ * warm-up decode, time each with HIP events on `stream`, and keep the fastest
+ * for the form `p` resolves to.  Synchronous.
+ *   best_out  host [2], may be NULL: the chosen blocks_per_cu and register_chunks
+ *   ms_out    host [2*max_blocks_per_cu], may be NULL: time of candidate
+ *             (variant v, blocks b) at [v*max_blocks_per_cu + b - 1]; v = 0 is the
+ *             default chunking, v = 1 register_chunks = 0 (streamed form only,
+ *             otherwise -1)
+ * Scratch outputs are allocated and freed inside the call. */
+lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, const lpdec_params *p,
+                            int32_t max_blocks_per_cu, int32_t *best_out, float *ms_out, void *stream);
+
 /* The check-node operation alone: z_k = Pi_PPd(v_k) for `count` vectors of
  * degree d (2 <= d <= LPDEC_MAX_CHECK_DEGREE), Algorithm 2 / Sec. 4.4.
  *   v, z  device [count*d] FP32, row-major (z may not alias v). */

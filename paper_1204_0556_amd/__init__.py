@@ -21,7 +21,8 @@ __all__ = [
     "LpdecError", "FLAG_CONVERGED", "FLAG_INTEGRAL", "FLAG_CODEWORD", "FLAG_CERTIFIED", "FLAG_INVALID",
     "MODE_AUTO", "MODE_RESIDENT", "MODE_STREAMED", "MODE_PERSISTENT_GLOBAL", "STORAGE_FP32", "STORAGE_FP16",
     "MAX_CHECK_DEGREE", "library_path", "Server", "EXECUTOR_GPU", "EXECUTOR_HOST_NULL",
-    "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE",
+    "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE", "decode_dual", "evaluate", "evaluate_multi",
+    "EVAL_WORD_ERROR", "EVAL_CODEWORD", "EVAL_ML_ERROR",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -33,6 +34,7 @@ STORAGE_FP32, STORAGE_FP16 = 0, 1
 STATE_IN, STATE_OUT = 0x1, 0x2
 EXECUTOR_GPU, EXECUTOR_HOST_NULL = 0, 1
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
+EVAL_WORD_ERROR, EVAL_CODEWORD, EVAL_ML_ERROR = 0x01, 0x02, 0x04
 MAX_CHECK_DEGREE = 8
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED", -5: "EBUSY"}
@@ -53,6 +55,13 @@ class _Info(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
                 ("min_check_degree", ctypes.c_int32), ("max_check_degree", ctypes.c_int32),
                 ("resident_capable", ctypes.c_int32), ("threads_per_frame", ctypes.c_int32)]
+
+
+class _LaunchInfo(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("threads", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
+                ("vgprs", ctypes.c_int32), ("runtime_blocks_per_cu", ctypes.c_int32),
+                ("resource_blocks_per_cu", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("register_chunks", ctypes.c_int32)]
 
 
 class _ServerConfig(ctypes.Structure):
@@ -92,6 +101,19 @@ def _load():
     lib.lpdec_decode_multi.argtypes = [P(vp), i32, i32, P(i32), P(i64), vp, i64, P(_Params), vp, P(i64), i64,
                                        vp, vp, vp]
     lib.lpdec_decode_multi.restype = ctypes.c_int
+    lib.lpdec_code_launch_info.argtypes = [vp, P(_Params), P(_LaunchInfo)]
+    lib.lpdec_code_launch_info.restype = ctypes.c_int
+    lib.lpdec_code_set_tuning.argtypes = [vp, i32, i32, i32]
+    lib.lpdec_code_set_tuning.restype = ctypes.c_int
+    lib.lpdec_autotune.argtypes = [vp, i32, vp, P(_Params), i32, P(i32), P(ctypes.c_float), vp]
+    lib.lpdec_autotune.restype = ctypes.c_int
+    lib.lpdec_decode_dual.argtypes = [vp, i32, vp, P(_Params), vp, vp, vp, vp]
+    lib.lpdec_decode_dual.restype = ctypes.c_int
+    lib.lpdec_evaluate.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.lpdec_evaluate.restype = ctypes.c_int
+    lib.lpdec_evaluate_multi.argtypes = [P(vp), i32, i32, P(i32), P(i64), vp, i64, vp, P(i64), i64, vp,
+                                         vp, vp, vp, vp, vp]
+    lib.lpdec_evaluate_multi.restype = ctypes.c_int
     lib.lpdec_project.argtypes = [i32, i32, vp, vp, vp]
     lib.lpdec_project.restype = ctypes.c_int
     lib.lpdec_server_default_config.restype = _ServerConfig
@@ -191,6 +213,37 @@ class Code:
         _check(_lib.lpdec_code_get_info(self.handle, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in _Info._fields_}
 
+    def launch_info(self, **params) -> dict:
+        """The launch a decode with these parameters (mode, storage) would use."""
+        p = _params(**params)
+        li = _LaunchInfo()
+        _check(_lib.lpdec_code_launch_info(self.handle, ctypes.byref(p), ctypes.byref(li)))
+        return {k: getattr(li, k) for k, _ in _LaunchInfo._fields_}
+
+    def set_tuning(self, mode: int, blocks_per_cu: int = 0, register_chunks: int = -1):
+        _check(_lib.lpdec_code_set_tuning(self.handle, int(mode), int(blocks_per_cu), int(register_chunks)))
+
+    def autotune(self, llr, max_blocks_per_cu: int = 4, stream=None, **params):
+        """Time decodes of the sample batch llr (float32 [B, n] CUDA tensor) over the
+        launch candidates and keep the fastest.  Returns ((blocks_per_cu,
+        register_chunks), {(register_chunks, blocks_per_cu): ms})."""
+        torch = _torch()
+        B = int(llr.shape[0]) if llr.dim() == 2 else 1
+        if llr.numel() != B * self.n:
+            raise ValueError("llr must be [batch, n]")
+        p = _params(**params)
+        mb = int(max_blocks_per_cu)
+        best = (ctypes.c_int32 * 2)()
+        ms = (ctypes.c_float * (2 * mb))()
+        _check(_lib.lpdec_autotune(self.handle, B, _dev_ptr(llr, torch.float32, "llr"), ctypes.byref(p),
+                                   mb, best, ms, _stream(stream)))
+        times = {}
+        for v in range(2):
+            for b in range(mb):
+                if ms[v * mb + b] >= 0:
+                    times[(-1 if v == 0 else 0, b + 1)] = float(ms[v * mb + b])
+        return (best[0], best[1]), times
+
     def close(self):
         if self._h:
             _lib.lpdec_code_destroy(self._h)
@@ -219,6 +272,70 @@ def decode(code: Code, llr, out=None, stream=None, **params):
                              _dev_ptr(x, torch.float32, "x"), _dev_ptr(it, torch.int32, "iters"),
                              _dev_ptr(fl, torch.uint8, "flags"), _stream(stream)))
     return x, it, fl
+
+
+def decode_dual(code: Code, llr, out=None, stream=None, mu=None, max_iter=None):
+    """Dual subgradient ascent (Appendix A) on llr (float32 [B, n] CUDA tensor) with
+    step mu.  Returns (x [B,n] f32 in {0,1}, iters [B] i32, flags [B] u8)."""
+    torch = _torch()
+    B = int(llr.shape[0]) if llr.dim() == 2 else 1
+    if llr.numel() != B * code.n:
+        raise ValueError("llr must be [batch, n]")
+    if out is None:
+        out = (torch.empty((B, code.n), dtype=torch.float32, device=llr.device),
+               torch.empty(B, dtype=torch.int32, device=llr.device),
+               torch.empty(B, dtype=torch.uint8, device=llr.device))
+    x, it, fl = out
+    p = _params(mu=mu, max_iter=max_iter)
+    _check(_lib.lpdec_decode_dual(code.handle, B, _dev_ptr(llr, torch.float32, "llr"), ctypes.byref(p),
+                                  _dev_ptr(x, torch.float32, "x"), _dev_ptr(it, torch.int32, "iters"),
+                                  _dev_ptr(fl, torch.uint8, "flags"), _stream(stream)))
+    return x, it, fl
+
+
+def _eval_out(F, dev):
+    torch = _torch()
+    return (torch.empty(F, dtype=torch.int32, device=dev), torch.empty(F, dtype=torch.float64, device=dev),
+            torch.empty(F, dtype=torch.float64, device=dev), torch.empty(F, dtype=torch.uint8, device=dev))
+
+
+def evaluate(code: Code, llr, x, sent=None, stream=None):
+    """Per-frame (bit_errors i32, cost_hat f64, cost_sent f64, outcome u8) of the
+    rounded estimate x against the transmitted word (None: all-zero)."""
+    torch = _torch()
+    B = int(llr.shape[0]) if llr.dim() == 2 else 1
+    if llr.numel() != B * code.n or x.numel() != B * code.n:
+        raise ValueError("llr and x must be [batch, n]")
+    if sent is not None and sent.numel() != B * code.n:
+        raise ValueError("sent must be [batch, n]")
+    be, ch, cs, oc = _eval_out(B, llr.device)
+    sp = _dev_ptr(sent, torch.uint8, "sent") if sent is not None else None
+    _check(_lib.lpdec_evaluate(code.handle, B, _dev_ptr(llr, torch.float32, "llr"), _dev_ptr(x, torch.float32, "x"),
+                               sp, _dev_ptr(be, torch.int32, "bit_errors"), _dev_ptr(ch, torch.float64, "cost_hat"),
+                               _dev_ptr(cs, torch.float64, "cost_sent"), _dev_ptr(oc, torch.uint8, "outcome"),
+                               _stream(stream)))
+    return be, ch, cs, oc
+
+
+def evaluate_multi(codes, code_of_frame, llr_offset, llr, x, x_offset, sent=None, stream=None):
+    """evaluate() over frames of several codes laid out as for decode_multi."""
+    torch = _torch()
+    cof = np.ascontiguousarray(code_of_frame, dtype=np.int32)
+    lo = np.ascontiguousarray(llr_offset, dtype=np.int64)
+    xo = np.ascontiguousarray(x_offset, dtype=np.int64)
+    F = int(cof.size)
+    be, ch, cs, oc = _eval_out(F, llr.device)
+    handles = (ctypes.c_void_p * len(codes))(*[c.handle.value for c in codes])
+    sp = _dev_ptr(sent, torch.uint8, "sent") if sent is not None else None
+    P = ctypes.POINTER
+    _check(_lib.lpdec_evaluate_multi(handles, len(codes), F, cof.ctypes.data_as(P(ctypes.c_int32)),
+                                     lo.ctypes.data_as(P(ctypes.c_int64)), _dev_ptr(llr, torch.float32, "llr"),
+                                     int(llr.numel()), _dev_ptr(x, torch.float32, "x"),
+                                     xo.ctypes.data_as(P(ctypes.c_int64)), int(x.numel()), sp,
+                                     _dev_ptr(be, torch.int32, "bit_errors"), _dev_ptr(ch, torch.float64, "cost_hat"),
+                                     _dev_ptr(cs, torch.float64, "cost_sent"), _dev_ptr(oc, torch.uint8, "outcome"),
+                                     _stream(stream)))
+    return be, ch, cs, oc
 
 
 def decode_state(code: Code, llr, z=None, u=None, state_in=False, state_out=True, stream=None, **params):

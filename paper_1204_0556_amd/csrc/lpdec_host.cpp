@@ -339,12 +339,62 @@ void streamed_config(const Shape &s, bool half, LaunchConfig *cfg) {
     cfg->state_stride = 0;
 }
 
-int occupancy_grid(const LaunchConfig &cfg, int frames) {
+// Workgroups of this configuration one compute unit can hold at once, from the
+// kernel's registers, its LDS and its size: gfx950 has 4 SIMDs per CU, 512
+// VGPRs per lane per SIMD (allocated in blocks of 8), at most 8 waves per SIMD
+// and 160 KB of LDS per CU.
+int resource_blocks_per_cu(const LaunchConfig &cfg, const KernelQuery &q) {
+    const int waves = (cfg.threads + kWave - 1) / kWave;
+    const int per_simd = (waves + 3) / 4;
+    const int vg = std::max(8, (q.vgprs + 7) / 8 * 8);
+    const int waves_per_simd = std::min(8, 512 / vg);
+    int by_regs = waves_per_simd / per_simd;
+    const size_t lds = cfg.lds_bytes + (size_t)q.static_lds;
+    int by_lds = lds > 0 ? (int)((160 * 1024) / lds) : 32;
+    return std::max(1, std::min(by_regs, by_lds));
+}
+
+// Workgroups per CU a launch uses: the code's tuned value for the form, else
+// the runtime's occupancy estimate.
+int blocks_per_cu(const LaunchConfig &cfg, const lpdec_code *code) {
+    const int tuned = code ? code->tune_bpc[static_cast<int>(cfg.form)] : 0;
+    if (tuned > 0) return tuned;
+    KernelQuery q{};
+    if (decode_query(cfg, &q) != hipSuccess || q.occupancy < 1) return 1;
+    return q.occupancy;
+}
+
+int occupancy_grid(const LaunchConfig &cfg, int frames, const lpdec_code *code) {
     DeviceInfo di = device_info();
     const int cus = di.cus > 0 ? di.cus : 256;
-    int per_cu = 0;
-    if (decode_occupancy(cfg, &per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
-    return std::max(1, std::min(frames, cus * per_cu));
+    return std::max(1, std::min(frames, cus * blocks_per_cu(cfg, code)));
+}
+
+lpdec_status check_params(const lpdec_params *p);
+
+// The form and launch configuration a decode of these codes with these
+// parameters uses (the mode resolution of every decode entry point).
+lpdec_status resolve_config(const Shape &s, const lpdec_params &p, bool scattered, LaunchConfig *cfg,
+                            const lpdec_code *code) {
+    const bool half = p.storage == LPDEC_STORAGE_FP16;
+    int mode = p.mode;
+    if (half && mode != LPDEC_MODE_STREAMED && mode != LPDEC_MODE_AUTO)
+        return fail(LPDEC_EUNSUPPORTED, "FP16 storage applies to the streamed form only");
+    if (mode == LPDEC_MODE_AUTO) mode = half ? LPDEC_MODE_STREAMED : LPDEC_MODE_RESIDENT;
+    if (mode == LPDEC_MODE_RESIDENT && !resident_config(s, cfg)) {
+        if (p.mode == LPDEC_MODE_RESIDENT)
+            return fail(LPDEC_EUNSUPPORTED, "the register-resident form does not fit this code");
+        mode = LPDEC_MODE_PERSISTENT_GLOBAL;
+    }
+    if (mode == LPDEC_MODE_PERSISTENT_GLOBAL) persistent_global_config(s, cfg);
+    if (mode == LPDEC_MODE_STREAMED) {
+        if (scattered)
+            return fail(LPDEC_EUNSUPPORTED, "the streamed form decodes one dense batch of one code per call");
+        streamed_config(s, half, cfg);
+        const int ch = code ? code->tune_chunks[static_cast<int>(Form::Streamed)] : -1;
+        if (ch == 0) cfg->cpt_tmpl = 0;
+    }
+    return LPDEC_OK;
 }
 
 lpdec_status check_params(const lpdec_params *p) {
@@ -360,23 +410,6 @@ lpdec_status check_params(const lpdec_params *p) {
 }
 
 // Acquire the workspace of the call's (first) code for exclusive use on `stream`.
-struct WsGuard {
-    Workspace &ws;
-    hipStream_t stream;
-    std::unique_lock<std::mutex> lk;
-    WsGuard(Workspace &w, hipStream_t s) : ws(w), stream(s), lk(w.mu) {
-        if (ws.last) (void)hipStreamWaitEvent(stream, ws.last, 0);
-    }
-    ~WsGuard() { (void)done(); }
-    hipError_t done() {
-        if (!ws.last) {
-            hipError_t e = hipEventCreateWithFlags(&ws.last, hipEventDisableTiming);
-            if (e != hipSuccess) return e;
-        }
-        return hipEventRecord(ws.last, stream);
-    }
-};
-
 }  // namespace
 
 // Core decode over a set of codes.  With llr_off / x_off (host arrays) the frames
@@ -410,21 +443,8 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
     const Shape s = shape_of(codes, ncodes);
     LaunchConfig cfg{};
     const bool half = p.storage == LPDEC_STORAGE_FP16;
-    int mode = p.mode;
-    if (half && mode != LPDEC_MODE_STREAMED && mode != LPDEC_MODE_AUTO)
-        return fail(LPDEC_EUNSUPPORTED, "FP16 storage applies to the streamed form only");
-    if (mode == LPDEC_MODE_AUTO) mode = half ? LPDEC_MODE_STREAMED : LPDEC_MODE_RESIDENT;
-    if (mode == LPDEC_MODE_RESIDENT && !resident_config(s, &cfg)) {
-        if (p.mode == LPDEC_MODE_RESIDENT)
-            return fail(LPDEC_EUNSUPPORTED, "the register-resident form does not fit this code");
-        mode = LPDEC_MODE_PERSISTENT_GLOBAL;
-    }
-    if (mode == LPDEC_MODE_PERSISTENT_GLOBAL) persistent_global_config(s, &cfg);
-    if (mode == LPDEC_MODE_STREAMED) {
-        if (ncodes > 1 || code_of_frame || llr_off || done)
-            return fail(LPDEC_EUNSUPPORTED, "the streamed form decodes one dense batch of one code per call");
-        streamed_config(s, half, &cfg);
-    }
+    st = resolve_config(s, p, ncodes > 1 || code_of_frame || llr_off || done, &cfg, codes[0]);
+    if (st != LPDEC_OK) return st;
 
     Workspace &ws = ws_in ? *ws_in : c0->ws;
     WsGuard guard(ws, stream);
@@ -487,7 +507,7 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
     StreamArgs sa{};
 
     if (cfg.form == Form::Resident || cfg.form == Form::PersistentGlobal) {
-        cfg.grid = occupancy_grid(cfg, nframes);
+        cfg.grid = occupancy_grid(cfg, nframes, codes[0]);
         HIP_TRY(ws.queue.ensure(sizeof(int)));
         fb.queue = static_cast<int *>(ws.queue.p);
         HIP_TRY(launch_fill_i32(fb.queue, 0, 1, stream));
@@ -530,7 +550,7 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
             sa.gmu = static_cast<float *>(ws.gmu.p);
             sa.gmu_stride = s.nmax;
         }
-        cfg.grid = occupancy_grid(cfg, nframes);
+        cfg.grid = occupancy_grid(cfg, nframes, codes[0]);
         if (cfg.slot_mode == 0) {
             HIP_TRY(ws.gslots.ensure(sizeof(float) * (size_t)cfg.grid * cfg.slot_stride));
             sa.gslots = static_cast<float *>(ws.gslots.p);
@@ -548,8 +568,7 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
             const int cnt = std::min(block, p.max_iter - issued);
             for (int k = 0; k < cnt; ++k) {
                 ip.launch = issued + k;
-                hipError_t e = launch_fill_i32(sa.active_count, 0, 1, stream);
-                if (e == hipSuccess) e = launch_decode(cfg, codes_dev, fb, ip, sio, sa, stream);
+                hipError_t e = launch_decode(cfg, codes_dev, fb, ip, sio, sa, stream);
                 if (e != hipSuccess) {
                     rs = fail(LPDEC_EDEVICE, "streamed launch failed: %s", hipGetErrorString(e));
                     break;
@@ -558,8 +577,8 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
             if (rs != LPDEC_OK) break;
             issued += cnt;
             const int slot = blk & 1;
-            hipError_t e = hipMemcpyAsync(ws.host_active + slot, sa.active_count, sizeof(int), hipMemcpyDeviceToHost,
-                                          stream);
+            hipError_t e = hipMemcpyAsync(ws.host_active + slot, sa.active_count + ((issued - 1) & 1), sizeof(int),
+                                          hipMemcpyDeviceToHost, stream);
             if (e == hipSuccess) e = hipEventRecord(ev[slot], stream);
             if (e != hipSuccess) {
                 rs = fail(LPDEC_EDEVICE, "progress copy failed: %s", hipGetErrorString(e));
@@ -636,6 +655,128 @@ lpdec_status lpdec_code_get_info(const lpdec_code *code, lpdec_code_info *info) 
     info->max_check_degree = code->dc.dmax;
     info->resident_capable = code->resident_ok ? 1 : 0;
     info->threads_per_frame = code->dc.waves * kWave;
+    return LPDEC_OK;
+}
+
+static int form_of_mode(int32_t mode) {
+    switch (mode) {
+        case LPDEC_MODE_RESIDENT: return static_cast<int>(Form::Resident);
+        case LPDEC_MODE_PERSISTENT_GLOBAL: return static_cast<int>(Form::PersistentGlobal);
+        case LPDEC_MODE_STREAMED: return static_cast<int>(Form::Streamed);
+        default: return -1;
+    }
+}
+
+static int32_t mode_of_form(Form f) {
+    switch (f) {
+        case Form::Resident: return LPDEC_MODE_RESIDENT;
+        case Form::PersistentGlobal: return LPDEC_MODE_PERSISTENT_GLOBAL;
+        default: return LPDEC_MODE_STREAMED;
+    }
+}
+
+lpdec_status lpdec_code_launch_info(const lpdec_code *code, const lpdec_params *pin, lpdec_launch_info *out) {
+    if (!code || !out) return fail(LPDEC_EINVAL, "code and out must not be NULL");
+    lpdec_params p = pin ? *pin : lpdec_default_params();
+    lpdec_status st = check_params(&p);
+    if (st != LPDEC_OK) return st;
+    LaunchConfig cfg{};
+    st = resolve_config(shape_of(&code, 1), p, false, &cfg, code);
+    if (st != LPDEC_OK) return st;
+    KernelQuery q{};
+    hipError_t e = decode_query(cfg, &q);
+    if (e != hipSuccess) return fail(LPDEC_EDEVICE, "kernel query failed: %s", hipGetErrorString(e));
+    out->mode = mode_of_form(cfg.form);
+    out->threads = cfg.threads;
+    out->lds_bytes = (int32_t)cfg.lds_bytes;
+    out->vgprs = q.vgprs;
+    out->runtime_blocks_per_cu = q.occupancy;
+    out->resource_blocks_per_cu = resource_blocks_per_cu(cfg, q);
+    out->blocks_per_cu = blocks_per_cu(cfg, code);
+    out->register_chunks = cfg.cpt_tmpl;
+    return LPDEC_OK;
+}
+
+lpdec_status lpdec_code_set_tuning(lpdec_code *code, int32_t mode, int32_t bpc, int32_t chunks) {
+    if (!code) return fail(LPDEC_EINVAL, "code must not be NULL");
+    const int f = form_of_mode(mode);
+    if (f < 0) return fail(LPDEC_EINVAL, "mode must be RESIDENT, STREAMED or PERSISTENT_GLOBAL (got %d)", mode);
+    if (bpc < 0 || bpc > 32) return fail(LPDEC_EINVAL, "blocks_per_cu must lie in 0..32 (got %d)", bpc);
+    if (chunks != -1 && chunks != 0 && chunks != 2)
+        return fail(LPDEC_EINVAL, "register_chunks must be -1, 0 or 2 (got %d)", chunks);
+    code->tune_bpc[f] = bpc;
+    code->tune_chunks[f] = chunks;
+    return LPDEC_OK;
+}
+
+lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, const lpdec_params *pin,
+                            int32_t max_bpc, int32_t *best_out, float *ms_out, void *stream_v) {
+    if (!code || !llr) return fail(LPDEC_EINVAL, "code and llr must not be NULL");
+    if (batch < 1) return fail(LPDEC_EINVAL, "batch must be >= 1");
+    if (max_bpc < 1 || max_bpc > 32) return fail(LPDEC_EINVAL, "max_blocks_per_cu must lie in 1..32");
+    lpdec_params p = pin ? *pin : lpdec_default_params();
+    lpdec_status st = check_params(&p);
+    if (st != LPDEC_OK) return st;
+    LaunchConfig cfg{};
+    const lpdec_code *one = code;
+    st = resolve_config(shape_of(&one, 1), p, false, &cfg, nullptr);
+    if (st != LPDEC_OK) return st;
+    const int f = static_cast<int>(cfg.form);
+    const int nvar = (cfg.form == Form::Streamed && cfg.cpt_tmpl > 0) ? 2 : 1;
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    const size_t n = (size_t)code->dc.n;
+    float *x = nullptr;
+    int32_t *it = nullptr;
+    uint8_t *fl = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const int saved = code->tune_bpc[f], saved_ch = code->tune_chunks[f];
+    int best = 0, best_ch = -1;
+    float best_ms = 0.0f;
+    if (ms_out)
+        for (int k = 0; k < 2 * max_bpc; ++k) ms_out[k] = -1.0f;
+    auto run = [&]() -> lpdec_status {
+        HIP_TRY(hipMalloc(&x, sizeof(float) * n * batch));
+        HIP_TRY(hipMalloc(&it, sizeof(int32_t) * batch));
+        HIP_TRY(hipMalloc(&fl, batch));
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        for (int v = 0; v < nvar; ++v) {
+            const int ch = v == 0 ? -1 : 0;
+            code->tune_chunks[f] = ch;
+            for (int b = 0; b <= max_bpc; ++b) {
+                code->tune_bpc[f] = b == 0 ? 1 : b;  // b = 0: untimed warm-up
+                HIP_TRY(hipEventRecord(e0, stream));
+                lpdec_status r = lpdec_decode_core(&one, 1, batch, nullptr, nullptr, nullptr, llr, &p, x, it, fl,
+                                                   nullptr, nullptr, 0, stream, nullptr, nullptr);
+                if (r != LPDEC_OK) return r;
+                HIP_TRY(hipEventRecord(e1, stream));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (b == 0) continue;
+                if (ms_out) ms_out[v * max_bpc + b - 1] = ms;
+                if (best == 0 || ms < best_ms) { best = b; best_ch = ch; best_ms = ms; }
+            }
+        }
+        return LPDEC_OK;
+    };
+    st = run();
+    if (x) (void)hipFree(x);
+    if (it) (void)hipFree(it);
+    if (fl) (void)hipFree(fl);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st != LPDEC_OK) {
+        code->tune_bpc[f] = saved;
+        code->tune_chunks[f] = saved_ch;
+        return st;
+    }
+    code->tune_bpc[f] = best;
+    code->tune_chunks[f] = best_ch;
+    if (best_out) {
+        best_out[0] = best;
+        best_out[1] = best_ch;
+    }
     return LPDEC_OK;
 }
 

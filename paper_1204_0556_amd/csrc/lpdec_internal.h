@@ -87,7 +87,8 @@ struct StreamArgs {
     void *z;                // [frames][E_int] fp32 or fp16
     void *u;
     StreamFrame *st;        // [frames]
-    int *active_count;      // device counter of frames still running after this launch
+    int *active_count;      // [2] frames still running after a launch: launch k counts into
+                            // entry k & 1 and clears the other one for launch k + 1
     float *gslots;          // [workgroups][slot_stride] slot scratch when slots live in global memory
     float *gmu;             // gamma/mu in internal variable order: [workgroups or frames][gmu_stride]
     unsigned *gxprev;       // accumulator mode, persistent form: previous x bits [workgroups][gmu_stride]
@@ -119,7 +120,14 @@ hipError_t launch_decode(const LaunchConfig &cfg, const DevCode *codes_dev, cons
 hipError_t launch_stream_init(const DevCode *codes_dev, int nframes, const LaunchConfig &cfg,
                               const FrameBatch &fb, const StateIO &sio, const StreamArgs &sa,
                               const IterParams &ip, hipStream_t stream);
-hipError_t decode_occupancy(const LaunchConfig &cfg, int *blocks_per_cu);
+// Resources of the kernel a configuration selects, and the runtime's occupancy
+// estimate for it (workgroups per compute unit).
+struct KernelQuery {
+    int occupancy;
+    int vgprs;
+    int static_lds;
+};
+hipError_t decode_query(const LaunchConfig &cfg, KernelQuery *q);
 hipError_t launch_stream_export(const DevCode *codes_dev, int nframes, int E_int, bool half, const StateIO &sio,
                                 const StreamArgs &sa, hipStream_t stream);
 hipError_t launch_project(int d, int count, const float *v, float *z, hipStream_t stream);

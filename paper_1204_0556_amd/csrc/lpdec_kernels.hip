@@ -380,13 +380,19 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             smask = __ballot(act);
         }
     };
+    if constexpr (!PERSIST) {
+        if (blockIdx.x == 0 && tid == 0) sa.active_count[(ip.launch + 1) & 1] = 0;  // next launch's counter
+    }
     int pending = -1;  // next frame, when already chosen (and prefetched)
     for (;;) {
         int f;
         if constexpr (PERSIST) {
+            // the frame index and the workgroup votes below are moved to scalar
+            // registers: branches on them are then uniform, so the frame loop
+            // keeps one shape for all lanes (lane 0 fetches the next frame)
             if (tid == 0) s_frame = atomicAdd(fb.queue, 1);
             __syncthreads();
-            f = s_frame;
+            f = __builtin_amdgcn_readfirstlane(s_frame);
             __syncthreads();
         } else {
             f = pending >= 0 ? pending : next_active();
@@ -459,7 +465,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 for (int i = tid; i < C.n; i += NT) gmu_row[i] = gam[C.var_orig[i]] * ip.mu_inv;
         }
         if constexpr (PERSIST) {
-            if (__syncthreads_or(bad)) {
+            if (__builtin_amdgcn_readfirstlane(__syncthreads_or(bad))) {
                 for (int i = tid; i < C.n; i += NT)
                     fb.x_out[(fb.x_off ? fb.x_off[f] : (int64_t)f * C.n) + i] = 0.5f;
                 __syncthreads();
@@ -760,7 +766,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             if (tid == 0) {
                 sa.st[f].iter = it;
                 if (fin) sa.st[f].done = 1;
-                else atomicAdd(sa.active_count, 1);
+                else atomicAdd(sa.active_count + (ip.launch & 1), 1);
             }
             if (!fin) {
                 wg_barrier<LBAR>();  // LDS reuse by the next frame of this workgroup
@@ -840,6 +846,7 @@ __global__ void __launch_bounds__(256)
 k_stream_init(const DevCode *__restrict__ codes, FrameBatch fb, StateIO sio, StreamArgs sa, float mu_inv) {
     const int f = blockIdx.x;
     if (f >= fb.nframes) return;
+    if (f == 0 && threadIdx.x < 2) sa.active_count[threadIdx.x] = 0;
     const int ci = fb.code_of_frame ? fb.code_of_frame[f] : 0;
     const DevCode &C = codes[ci];
     const int64_t loff = fb.llr_off ? fb.llr_off[f] : (int64_t)f * C.n;
@@ -894,7 +901,7 @@ hipError_t launch_stream_init(const DevCode *codes_dev, int nframes, const Launc
 template <int DMIN, int DMAX, int CPT, int VPT, bool RES, bool PERSIST, int SM, bool HALF, int MAXT = kMaxThreads,
           int DV = 0>
 static hipError_t go(const LaunchConfig &cfg, const DevCode *codes, const FrameBatch &fb, const IterParams &ip,
-                     const StateIO &sio, const StreamArgs &sa, hipStream_t stream, int *occ) {
+                     const StateIO &sio, const StreamArgs &sa, hipStream_t stream, KernelQuery *q) {
     if (cfg.threads > MAXT) return hipErrorInvalidConfiguration;
     auto kern = k_decode<DMIN, DMAX, CPT, VPT, RES, PERSIST, SM, HALF, MAXT, DV>;
     if (cfg.lds_bytes > 64 * 1024) {
@@ -902,7 +909,14 @@ static hipError_t go(const LaunchConfig &cfg, const DevCode *codes, const FrameB
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg.lds_bytes);
         if (e != hipSuccess) return e;
     }
-    if (occ) return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, kern, cfg.threads, cfg.lds_bytes);
+    if (q) {
+        hipFuncAttributes fa{};
+        hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kern));
+        if (e != hipSuccess) return e;
+        q->vgprs = fa.numRegs;
+        q->static_lds = (int)fa.sharedSizeBytes;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&q->occupancy, kern, cfg.threads, cfg.lds_bytes);
+    }
     hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(cfg.threads), cfg.lds_bytes, stream, codes, fb, ip, sio, sa,
                        cfg.lds_E, cfg.slot_stride, cfg.state_stride);
     return hipGetLastError();
@@ -911,8 +925,8 @@ static hipError_t go(const LaunchConfig &cfg, const DevCode *codes, const FrameB
 template <int DMIN, int DMAX>
 static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const FrameBatch &fb,
                            const IterParams &ip, const StateIO &sio, const StreamArgs &sa, hipStream_t stream,
-                           int *occ) {
-#define LPD_GO(...) return go<DMIN, DMAX, __VA_ARGS__>(cfg, codes, fb, ip, sio, sa, stream, occ)
+                           KernelQuery *q) {
+#define LPD_GO(...) return go<DMIN, DMAX, __VA_ARGS__>(cfg, codes, fb, ip, sio, sa, stream, q)
     switch (cfg.form) {
         case Form::Resident:
             if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4 && cfg.dv == 3) LPD_GO(2, 4, true, true, 1, false, 768, 3);
@@ -954,14 +968,14 @@ hipError_t launch_decode(const LaunchConfig &cfg, const DevCode *codes_dev, cons
     return go_range<2, 8>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
 }
 
-hipError_t decode_occupancy(const LaunchConfig &cfg, int *blocks_per_cu) {
+hipError_t decode_query(const LaunchConfig &cfg, KernelQuery *q) {
     FrameBatch fb{};
     IterParams ip{};
     StateIO sio{};
     StreamArgs sa{};
-    *blocks_per_cu = 0;
-    if (cfg.dclass == 0) return go_range<6, 6>(cfg, nullptr, fb, ip, sio, sa, nullptr, blocks_per_cu);
-    return go_range<2, 8>(cfg, nullptr, fb, ip, sio, sa, nullptr, blocks_per_cu);
+    *q = KernelQuery{};
+    if (cfg.dclass == 0) return go_range<6, 6>(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
+    return go_range<2, 8>(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
 }
 
 // Streamed form: copy the final lane-minor state back to CSR edge order.

@@ -57,6 +57,25 @@ struct Workspace {
     }
 };
 
+// Exclusive use of a workspace by one call: the call's stream first waits for
+// the previous user's work, and the destructor records this call's completion.
+struct WsGuard {
+    Workspace &ws;
+    hipStream_t stream;
+    std::unique_lock<std::mutex> lk;
+    WsGuard(Workspace &w, hipStream_t s) : ws(w), stream(s), lk(w.mu) {
+        if (ws.last) (void)hipStreamWaitEvent(stream, ws.last, 0);
+    }
+    ~WsGuard() { (void)done(); }
+    hipError_t done() {
+        if (!ws.last) {
+            hipError_t e = hipEventCreateWithFlags(&ws.last, hipEventDisableTiming);
+            if (e != hipSuccess) return e;
+        }
+        return hipEventRecord(ws.last, stream);
+    }
+};
+
 struct lpdec_code {
     lpdec::DevCode dc{};   // host copy with device pointers
     lpdec::DevCode *d_dc = nullptr;
@@ -64,6 +83,8 @@ struct lpdec_code {
     int device = -1;
     bool resident_ok = false;
     lpdec::LaunchConfig resident_cfg{};
+    int tune_bpc[3] = {0, 0, 0};     // workgroups per CU by form (0: runtime estimate)
+    int tune_chunks[3] = {-1, -1, -1};  // register-held chunks per wave by form (-1: default)
     Workspace ws;
     ~lpdec_code() {
         if (d_dc) (void)hipFree(d_dc);

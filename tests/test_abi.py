@@ -98,6 +98,17 @@ def test_multi_argument_checks(lib):
                                   ctypes.c_int64(0), None, None, None) == EINVAL
 
 
+def test_tuning_argument_checks(lib):
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    lib.lpdec_code_set_tuning.argtypes = [vp, i32, i32, i32]
+    assert lib.lpdec_code_set_tuning(None, 1, 1, -1) == EINVAL
+    lib.lpdec_code_launch_info.argtypes = [vp, vp, vp]
+    assert lib.lpdec_code_launch_info(None, None, None) == EINVAL
+    lib.lpdec_autotune.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp]
+    assert lib.lpdec_autotune(None, 1, None, None, 2, None, None, None) == EINVAL
+    assert "NULL" in lib.lpdec_last_error().decode()
+
+
 def test_default_params(lib):
     class P(ctypes.Structure):
         _fields_ = [("mu", ctypes.c_float), ("rho", ctypes.c_float), ("max_iter", ctypes.c_int32),
