@@ -248,6 +248,183 @@ def workload_precision(args, lp, W, torch):
     }
 
 
+def _timed(torch, fn, steps=1, warmup=1):
+    """Run fn warmup + steps times; return (last result, mean ms of the timed runs)
+    from HIP events on the current stream."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    out = None
+    for _ in range(steps):
+        out = fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return out, e0.elapsed_time(e1) / steps
+
+
+def _iteration_stats(it, err):
+    it = np.asarray(it, np.int64)
+    err = np.asarray(err, bool)
+    return {"all": round(float(it.mean()), 2),
+            "correct": round(float(it[~err].mean()), 2) if (~err).any() else None,
+            "erroneous": round(float(it[err].mean()), 2) if err.any() else None}
+
+
+def _clopper_pearson(k, n, a=0.05):
+    from scipy.stats import beta
+    lo = 0.0 if k == 0 else float(beta.ppf(a / 2, k, n - k + 1))
+    hi = 1.0 if k == n else float(beta.ppf(1 - a / 2, k + 1, n - k))
+    return [lo, hi]
+
+
+def workload_bsc(args, lp, W, torch):
+    """The random-code BSC study of Sec. 5.1: 100 random (3,6)-regular n = 1002 codes
+    (parallel edges removed, length-4 cycles kept), BSC crossover p in BSC_CROSSOVERS,
+    `--bsc-frames` frames per code and crossover, all codes in one batched launch per
+    crossover.  Reports WER, BER, the ML lower bound of Sec. 5.1 and the iteration
+    counts (all / correct / erroneous decodes), as in the ensemble figures."""
+    codes_h = W.bsc_ensemble()
+    codes = [lp.Code(H) for H in codes_h]
+    n = codes_h[0].n
+    F = args.bsc_frames
+    P = W.PAPER_PARAMS
+    cof = np.repeat(np.arange(len(codes_h), dtype=np.int32), F)
+    off = np.arange(cof.size, dtype=np.int64) * n
+    out, total_ms, total_bits, ops = {}, 0.0, 0, 0
+    for p in W.BSC_CROSSOVERS:
+        llr_h = np.concatenate([W.bsc_batch(H, F, p, tag="bsc-bench") for H in codes_h]).reshape(-1)
+        llr = torch.from_numpy(llr_h).cuda()
+        (x, it, fl), ms = _timed(torch, lambda: lp.decode_multi(codes, cof, off, llr, off, llr.numel(), **P),
+                                 steps=args.steps, warmup=args.warmup)
+        be, ch, cs, oc = lp.evaluate_multi(codes, cof, off, llr, x, off)
+        torch.cuda.synchronize()
+        be, oc, it_h = be.cpu().numpy(), oc.cpu().numpy(), it.cpu().numpy()
+        werr = (oc & lp.EVAL_WORD_ERROR) != 0
+        k = int(werr.sum())
+        frames = int(cof.size)
+        total_ms += ms
+        total_bits += frames * n
+        ops += algorithmic_ops_per_frame_iter(codes_h[0]) * int(it_h.astype(np.int64).sum())
+        out[str(p)] = {
+            "frames": frames, "word_errors": k, "wer": k / frames, "wer_ci95": _clopper_pearson(k, frames),
+            "ber": float(be.sum()) / (frames * n),
+            "ml_lower_bound_errors": int(((oc & lp.EVAL_ML_ERROR) != 0).sum()),
+            "ml_lower_bound_wer": float(((oc & lp.EVAL_ML_ERROR) != 0).mean()),
+            "iterations": _iteration_stats(it_h, werr),
+            "certified": int(((fl.cpu().numpy() & lp.FLAG_CERTIFIED) != 0).sum()),
+            "ms": round(ms, 3), "mbit_s": round(frames * n / (ms / 1e3) / 1e6, 1),
+        }
+    achieved = ops / (total_ms / 1e3) / 1e9
+    return {
+        "metric": METRIC, "value": round(total_bits / (total_ms / 1e3) / 1e6, 2), "unit": "Mbit/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total_ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"BSC ensemble: {len(codes_h)} random (3,6)-regular n={n} codes (parallel edges "
+                               f"removed), crossover p in {list(W.BSC_CROSSOVERS)}, {F} frames per code and p, "
+                               "all-zero codeword, mu=3 rho=1.9 max_iter=1000 tol=1e-5, one batched launch per p"},
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e3, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 2),
+                     "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_GOPS, 4), "traffic": None,
+                     "kernel": "k_decode (resident, multi-code)"},
+        "bsc": out,
+    }
+
+
+def workload_sweep(args, lp, W, torch):
+    """Parameter sensitivity of Sec. 5.2 on the (3,6) n = 2640 code: WER and decode time
+    against the stopping tolerance (2.2 dB, mu in {1,5,7}, rho = 1), against mu
+    (1.9/2.2/2.5 dB, eps = 1e-5, rho = 1), and against the over-relaxation rho
+    (2.8 dB, mu in {1,3,5,7})."""
+    H = W.gallager36(2640)
+    code = lp.Code(H)
+    F = args.sweep_frames
+    llrs = {}
+
+    def llr_at(snr):
+        if snr not in llrs:
+            llrs[snr] = torch.from_numpy(W.awgn_batch(H, F, snr, tag="sweep")).cuda()
+        return llrs[snr]
+
+    def point(snr, **kw):
+        prm = dict(W.PAPER_PARAMS)
+        prm.update(kw)
+        (x, it, fl), ms = _timed(torch, lambda: lp.decode(code, llr_at(snr), **prm), steps=1, warmup=1)
+        err = (x >= 0.5).any(dim=1).cpu().numpy()
+        it_h = it.cpu().numpy()
+        return {"wer": float(err.mean()), "word_errors": int(err.sum()), "ms": round(ms, 3),
+                "mean_iterations": round(float(it_h.mean()), 2), "us_per_frame": round(ms * 1e3 / F, 3)}
+
+    total_ms, points = 0.0, 0
+    eps = {}
+    for mu in (1.0, 5.0, 7.0):
+        for b in (4, 7, 10, 13, 17, 20):
+            r = point(2.2, mu=mu, rho=1.0, tol=2.0 ** -b)
+            eps[f"mu={mu:g},-log2(eps)={b}"] = r
+            total_ms += r["ms"]
+            points += 1
+    mus = {}
+    for snr in (1.9, 2.2, 2.5):
+        for mu in (0.5, 1.0, 2.0, 3.0, 5.0, 7.0, 10.0):
+            r = point(snr, mu=mu, rho=1.0, tol=1e-5)
+            mus[f"{snr}dB,mu={mu:g}"] = r
+            total_ms += r["ms"]
+            points += 1
+    rhos, speedup = {}, {}
+    for mu in (1.0, 3.0, 5.0, 7.0):
+        for rho in (1.0, 1.3, 1.6, 1.9):
+            r = point(2.8, mu=mu, rho=rho, tol=1e-5)
+            rhos[f"mu={mu:g},rho={rho:g}"] = r
+            total_ms += r["ms"]
+            points += 1
+        a, b = rhos[f"mu={mu:g},rho=1"], rhos[f"mu={mu:g},rho=1.9"]
+        speedup[f"mu={mu:g}"] = {"time": round(a["ms"] / b["ms"], 3),
+                                 "iterations": round(a["mean_iterations"] / b["mean_iterations"], 3)}
+    bits = points * F * H.n
+    return {
+        "metric": METRIC, "value": round(bits / (total_ms / 1e3) / 1e6, 2), "unit": "Mbit/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": round(total_ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"parameter sweeps: (3,6) n=2640, {F} frames per point, {points} points "
+                               "(eps at 2.2 dB, mu at 1.9/2.2/2.5 dB, rho at 2.8 dB), t_max=1000"},
+        "sweep": {"tolerance": eps, "mu": mus, "over_relaxation": rhos,
+                  "rho_1_over_rho_1.9": speedup},
+    }
+
+
+def workload_dual(args, lp, W, torch):
+    """Dual subgradient ascent (Appendix A) against ADMM on the (3,6) n = 2640 code:
+    the same frames, t_max = 1000, three step sizes, three Eb/N0."""
+    H = W.gallager36(2640)
+    code = lp.Code(H)
+    F = args.sweep_frames
+    out, total_ms, bits = {}, 0.0, 0
+    for snr in (2.5, 3.0, 3.5):
+        llr = torch.from_numpy(W.awgn_batch(H, F, snr, tag="dual-bench")).cuda()
+        (x, it, fl), ms = _timed(torch, lambda: lp.decode(code, llr, **W.PAPER_PARAMS))
+        err = (x >= 0.5).any(dim=1).cpu().numpy()
+        row = {"admm": {"wer": float(err.mean()), "iterations": _iteration_stats(it.cpu().numpy(), err),
+                        "ms": round(ms, 3)}}
+        for mu in (0.1, 0.25, 0.5):
+            (x, it, fl), ms = _timed(torch, lambda: lp.decode_dual(code, llr, mu=mu, max_iter=1000))
+            err = (x >= 0.5).any(dim=1).cpu().numpy()
+            conv = (fl.cpu().numpy() & lp.FLAG_CONVERGED) != 0
+            row[f"dual_mu={mu:g}"] = {"wer": float(err.mean()), "converged": float(conv.mean()),
+                                      "iterations": _iteration_stats(it.cpu().numpy(), err), "ms": round(ms, 3)}
+            total_ms += ms
+            bits += F * H.n
+        out[f"{snr}dB"] = row
+    return {
+        "metric": METRIC, "value": round(bits / (total_ms / 1e3) / 1e6, 2), "unit": "Mbit/s (dual subgradient)",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(total_ms, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "i32 (f64 decisions)", "data": "synthetic",
+        "config": {"workload": f"dual subgradient ascent vs ADMM: (3,6) n=2640, {F} frames at 2.5/3.0/3.5 dB, "
+                               "step mu in {0.1,0.25,0.5}, t_max=1000"},
+        "dual": out,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,7 +434,10 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=4096, help="oracle sample size (frames)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the plain and streamed comparisons")
-    ap.add_argument("--workload", default="headline", choices=["headline", "uneven", "precision", "serving"])
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "uneven", "precision", "serving", "bsc", "sweep", "dual"])
+    ap.add_argument("--bsc-frames", type=int, default=128, help="frames per code and crossover (bsc workload)")
+    ap.add_argument("--sweep-frames", type=int, default=4096, help="frames per point (sweep and dual workloads)")
     ap.add_argument("--serving-seconds", type=float, default=1.0,
                     help="length of the serving trace folded into the headline line (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -293,6 +473,15 @@ def main():
         return
     if args.workload == "precision":
         print(json.dumps(workload_precision(args, lp, W, torch)))
+        return
+    if args.workload == "bsc":
+        print(json.dumps(workload_bsc(args, lp, W, torch)))
+        return
+    if args.workload == "sweep":
+        print(json.dumps(workload_sweep(args, lp, W, torch)))
+        return
+    if args.workload == "dual":
+        print(json.dumps(workload_dual(args, lp, W, torch)))
         return
 
     modes = {"auto": lp.MODE_AUTO, "resident": lp.MODE_RESIDENT,
@@ -338,11 +527,16 @@ def main():
     form = "resident" if args.form in ("auto", "resident") and code.info["resident_capable"] else args.form
     if form == "auto":
         form = "persistent_global"
+    # per-SNR error rates and the ML lower bound of Sec. 5.1 (evaluation kernel)
+    _, _, _, ml_oc = lp.evaluate(code, llr, out[0])
+    ml_oc = ml_oc.cpu().numpy()
     fer = {}
     for b, s in enumerate(W.HEADLINE_SNRS):
         sl = slice(b * FRAMES_PER_SNR, (b + 1) * FRAMES_PER_SNR)
         errs = int(np.sum((x[sl] >= 0.5).any(axis=1)))
         fer[str(s)] = {"frame_errors": errs, "fer": errs / FRAMES_PER_SNR,
+                       "fer_ci95": _clopper_pearson(errs, FRAMES_PER_SNR),
+                       "ml_lower_bound_errors": int(((ml_oc[sl] & lp.EVAL_ML_ERROR) != 0).sum()),
                        "mean_iters": float(iters[sl].mean())}
 
     res = {
