@@ -321,17 +321,10 @@ void persistent_global_config(const Shape &s, LaunchConfig *cfg) {
 void streamed_config(const Shape &s, bool half, LaunchConfig *cfg) {
     cfg->form = Form::Streamed;
     cfg->slot_mode = slot_mode_for(s, &cfg->lds_bytes);
-    cfg->cpt_tmpl = (cfg->slot_mode == 1 && s.cpt <= 2) ? 2 : 0;
+    cfg->cpt_tmpl = (cfg->slot_mode == 1 && s.cpt <= 2 && s.dclass == 0) ? 2 : 0;
     cfg->dclass = s.dclass;
-    // register-held variable side (and its prefetch) when it fits: <= 8 per thread
-    const int vpt = (s.nmax + s.waves * kWave - 1) / (s.waves * kWave);
     cfg->vpt_tmpl = 0;
     cfg->dv = 0;
-    // (measured slower than reading gamma in phase B, so kept off)
-    if (false && cfg->cpt_tmpl == 2 && vpt <= 8 && s.waves * kWave <= 768) {
-        cfg->dv = (s.dv == 3 && vpt <= 4) ? 3 : 0;
-        cfg->vpt_tmpl = cfg->dv == 3 ? 4 : 8;
-    }
     cfg->half = half;
     cfg->threads = s.waves * kWave;
     cfg->lds_E = s.Emax;

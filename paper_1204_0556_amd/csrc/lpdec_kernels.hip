@@ -213,8 +213,9 @@ __device__ __forceinline__ float wave_sum(float x) {
 }
 
 // Workgroup barrier.  With LDS_ONLY the release/acquire fences cover LDS only, so
-// global loads still in flight (prefetched state) do not have to land first; the
-// phases exchange data through LDS alone in every form but the global-slot one.
+// global stores still in flight (the previous phase's z, u) do not have to land
+// first; the phases exchange data through LDS alone in every form but the
+// global-slot one.
 template <bool LDS_ONLY>
 __device__ __forceinline__ void wg_barrier() {
     if constexpr (LDS_ONLY) {
@@ -318,8 +319,11 @@ __device__ __forceinline__ void st_state(void *p, size_t i, float a) {
 // check l of each of them.  CPT > 0 keeps those chunks' z,u (and packed edge
 // metadata) in registers; CPT == 0 walks the chunks and re-reads state.
 // Variable side: thread t owns internal variables t, t + NT, ...
+// Streamed form with register-held chunks: the register budget is capped so
+// that two workgroups of <= 768 threads share a CU (6 waves per SIMD); one
+// workgroup's memory waits then overlap the other's arithmetic.
 template <int DMIN, int DMAX, int CPT, int VPT, bool RES, bool PERSIST, int SM, bool HALF, int MAXT, int DV>
-__global__ void __launch_bounds__(MAXT)
+__global__ void __launch_bounds__(MAXT, (!PERSIST && CPT > 0) ? (MAXT <= 768 ? 6 : 4) : 1)
 k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateIO sio, StreamArgs sa,
          int lds_E, int slot_stride, int state_stride) {
     // SM: where the slot exchange lives -- 0 global float slots, 1 LDS float slots,
@@ -345,12 +349,6 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
 
     constexpr int NC = CPT > 0 ? CPT : 1;
     float z[NC][DMAX], u[NC][DMAX];
-    // streamed form: the next unfinished frame's state, loaded during phase C
-    constexpr bool PREFETCH = !PERSIST && CPT > 0;
-    constexpr int NP = PREFETCH ? NC : 1;
-    float pz[NP][DMAX], pu[NP][DMAX];
-    float pg[PREFETCH && VPT > 0 ? VPT : 1];  // gamma/mu of the prefetched frame
-    int pf_f = -1;
     constexpr bool LBAR = SM != 0;  // phase barriers need only order LDS
     uint32_t meta[NC][DMAX];
     int cdeg[NC], coff[NC];
@@ -383,7 +381,6 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
     if constexpr (!PERSIST) {
         if (blockIdx.x == 0 && tid == 0) sa.active_count[(ip.launch + 1) & 1] = 0;  // next launch's counter
     }
-    int pending = -1;  // next frame, when already chosen (and prefetched)
     for (;;) {
         int f;
         if constexpr (PERSIST) {
@@ -395,8 +392,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             f = __builtin_amdgcn_readfirstlane(s_frame);
             __syncthreads();
         } else {
-            f = pending >= 0 ? pending : next_active();
-            pending = -1;
+            f = next_active();
         }
         if (f >= fb.nframes) break;
 
@@ -442,15 +438,8 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         // -- frame set-up: gamma/mu, invalid-input check ----------------------
         bool bad = false;
         if constexpr (VPT > 0) {
-            const bool have = PREFETCH && pf_f == f;
 #pragma unroll
             for (int t = 0; t < VPT; ++t) {
-                if constexpr (PREFETCH && VPT > 0) {
-                    if (have) {
-                        vg[t] = pg[t];
-                        continue;
-                    }
-                }
                 const int i = tid + t * NT;
                 float g = 0.0f;
                 if (i < C.n) {
@@ -542,17 +531,9 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
                     if constexpr (!RES) {
-                        const bool have = PREFETCH && pf_f == f;
 #pragma unroll
                         for (int e = 0; e < DMAX; ++e) {
                             if (cval[k] && e < cdeg[k]) {
-                                if constexpr (PREFETCH) {
-                                    if (have) {
-                                        z[k][e] = pz[k][e];
-                                        u[k][e] = pu[k][e];
-                                        continue;
-                                    }
-                                }
                                 const size_t p = coff[k] + e * kWave + lane;
                                 z[k][e] = ld_state<HALF>(gz, p);
                                 u[k][e] = ld_state<HALF>(gu, p);
@@ -703,7 +684,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 phase_a();
                 wg_barrier<LBAR>();
                 if (it > 1) {
-                    if (converged((it - 1) & 1)) { conv = true; break; }
+                    if (__builtin_amdgcn_readfirstlane(converged((it - 1) & 1))) { conv = true; break; }
                     if (it > ip.max_iter) break;
                 }
                 phase_b();
@@ -728,41 +709,13 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             wg_barrier<LBAR>();
             phase_b();
             wg_barrier<LBAR>();
-            if constexpr (PREFETCH) {
-                // next unfinished frame of this workgroup; its state streams in while
-                // phase C computes (the LDS-only barriers do not wait for it)
-                const int g = next_active();
-                pending = g;
-                pf_f = -1;
-                if (g < fb.nframes) {
-                    if constexpr (VPT > 0) {
-                        const float *gg = fb.llr + (int64_t)g * C.n;
-#pragma unroll
-                        for (int t = 0; t < VPT; ++t) {
-                            const int i = tid + t * NT;
-                            pg[t] = (i < C.n) ? gg[C.var_identity ? i : C.var_orig[i]] * ip.mu_inv : 0.0f;
-                        }
-                    }
-                    const size_t gb = (size_t)g * C.E_int;
-#pragma unroll
-                    for (int k = 0; k < CPT; ++k)
-#pragma unroll
-                        for (int e = 0; e < DMAX; ++e)
-                            if (cval[k] && e < cdeg[k]) {
-                                const size_t p = gb + coff[k] + e * kWave + lane;
-                                pz[k][e] = ld_state<HALF>(sa.z, p);
-                                pu[k][e] = ld_state<HALF>(sa.u, p);
-                            }
-                    pf_f = g;
-                }
-            }
             float rp = 0.0f, rd = 0.0f;
             phase_c(rp, rd);
             publish(0, rp, rd);
             wg_barrier<LBAR>();
             conv = converged(0);
             iters = it;
-            const bool fin = conv || it >= ip.max_iter;
+            const bool fin = __builtin_amdgcn_readfirstlane(conv || it >= ip.max_iter);
             if (tid == 0) {
                 sa.st[f].iter = it;
                 if (fin) sa.st[f].done = 1;
@@ -929,10 +882,13 @@ static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const 
 #define LPD_GO(...) return go<DMIN, DMAX, __VA_ARGS__>(cfg, codes, fb, ip, sio, sa, stream, q)
     switch (cfg.form) {
         case Form::Resident:
-            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4 && cfg.dv == 3) LPD_GO(2, 4, true, true, 1, false, 768, 3);
-            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8 && cfg.dv == 3) LPD_GO(2, 8, true, true, 1, false, 768, 3);
-            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4) LPD_GO(2, 4, true, true, 1, false, 768);
-            if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8) LPD_GO(2, 8, true, true, 1, false, 768);
+            // register budget: degree-6 codes only (the host never selects it otherwise)
+            if constexpr (DMIN == 6 && DMAX == 6) {
+                if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4 && cfg.dv == 3) LPD_GO(2, 4, true, true, 1, false, 768, 3);
+                if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8 && cfg.dv == 3) LPD_GO(2, 8, true, true, 1, false, 768, 3);
+                if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4) LPD_GO(2, 4, true, true, 1, false, 768);
+                if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8) LPD_GO(2, 8, true, true, 1, false, 768);
+            }
             break;
         case Form::PersistentGlobal:
             if (cfg.slot_mode == 1) LPD_GO(0, 0, false, true, 1, false);
@@ -940,16 +896,15 @@ static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const 
             LPD_GO(0, 0, false, true, 0, false);
         case Form::Streamed:
             if (cfg.slot_mode == 1) {
-                if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4 && cfg.dv == 3 && !cfg.half)
-                    LPD_GO(2, 4, false, false, 1, false, 768, 3);
-                if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4 && cfg.dv == 3 && cfg.half)
-                    LPD_GO(2, 4, false, false, 1, true, 768, 3);
-                if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8 && !cfg.half) LPD_GO(2, 8, false, false, 1, false, 768);
-                if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8 && cfg.half) LPD_GO(2, 8, false, false, 1, true, 768);
-                if (cfg.cpt_tmpl == 2 && !cfg.half) LPD_GO(2, 0, false, false, 1, false);
-                if (cfg.cpt_tmpl == 2 && cfg.half) LPD_GO(2, 0, false, false, 1, true);
-                if (cfg.cpt_tmpl == 0 && !cfg.half) LPD_GO(0, 0, false, false, 1, false);
-                if (cfg.cpt_tmpl == 0 && cfg.half) LPD_GO(0, 0, false, false, 1, true);
+                // register-held chunks: degree-6 codes only (DMAX = 8 register arrays spill)
+                if constexpr (DMIN == 6 && DMAX == 6) {
+                    if (cfg.cpt_tmpl == 2 && cfg.threads <= 768 && !cfg.half) LPD_GO(2, 0, false, false, 1, false, 768);
+                    if (cfg.cpt_tmpl == 2 && cfg.threads <= 768 && cfg.half) LPD_GO(2, 0, false, false, 1, true, 768);
+                    if (cfg.cpt_tmpl == 2 && !cfg.half) LPD_GO(2, 0, false, false, 1, false);
+                    if (cfg.cpt_tmpl == 2 && cfg.half) LPD_GO(2, 0, false, false, 1, true);
+                }
+                if (!cfg.half) LPD_GO(0, 0, false, false, 1, false);
+                LPD_GO(0, 0, false, false, 1, true);
             }
             if (cfg.slot_mode == 2) {
                 if (!cfg.half) LPD_GO(0, 0, false, false, 2, false);
