@@ -213,8 +213,10 @@ typedef struct {
     int32_t runtime_blocks_per_cu; /* the HIP runtime's occupancy estimate                */
     int32_t resource_blocks_per_cu;/* workgroups per CU that registers and LDS allow      */
     int32_t blocks_per_cu;         /* what decode launches of this code use now           */
-    int32_t register_chunks;       /* 64-check chunks whose z,u a wave keeps in registers
-                                      (0: re-read from memory in each phase)              */
+    int32_t variant;               /* streamed form: 0 z,u re-read from HBM in each phase;
+                                      1 two chunks per wave in registers, two workgroups
+                                      per CU; 2 as 1 with one workgroup per CU staging the
+                                      next frame in LDS (direct-to-LDS loads); -1 other forms */
 } lpdec_launch_info;
 
 /* The launch a decode of `code` with parameters `p` (NULL = defaults; mode and
@@ -224,24 +226,25 @@ lpdec_status lpdec_code_launch_info(const lpdec_code *code, const lpdec_params *
 
 /* Fix the launch of one form (LPDEC_MODE_RESIDENT, _STREAMED or
  * _PERSISTENT_GLOBAL) for this code.
- *   blocks_per_cu    workgroups per CU, 1..32; 0 restores the runtime's estimate
- *   register_chunks  streamed form only: 0 re-reads each chunk's z,u in every
- *                    phase, 2 keeps them in registers (when the code allows);
- *                    -1 restores the default.  Ignored by the other forms.
+ *   blocks_per_cu  workgroups per CU, 1..32; 0 restores the runtime's estimate
+ *   variant        streamed form only (see lpdec_launch_info.variant): 0, 1 or 2;
+ *                  a variant the code does not allow falls back to the next
+ *                  lower one; -1 restores the default (the highest allowed).
+ *                  Ignored by the other forms.
  * Not synchronised with decodes running on other threads. */
 lpdec_status lpdec_code_set_tuning(lpdec_code *code, int32_t mode, int32_t blocks_per_cu,
-                                   int32_t register_chunks);
+                                   int32_t variant);
 
 /* Autotuner: decode the caller's sample batch (device llr [batch*n]) with
  * parameters `p` once per candidate launch -- workgroups per CU 1..max_blocks_per_cu,
- * times register_chunks {default, 0} for the streamed form -- after one untimed
- * warm-up decode, time each with HIP events on `stream`, and keep the fastest
- * for the form `p` resolves to.  Synchronous.
- *   best_out  host [2], may be NULL: the chosen blocks_per_cu and register_chunks
- *   ms_out    host [2*max_blocks_per_cu], may be NULL: time of candidate
- *             (variant v, blocks b) at [v*max_blocks_per_cu + b - 1]; v = 0 is the
- *             default chunking, v = 1 register_chunks = 0 (streamed form only,
- *             otherwise -1)
+ * times the variants 0, 1, 2 the code allows for the streamed form -- after one
+ * untimed warm-up decode, time each with HIP events on `stream`, and keep the
+ * fastest for the form `p` resolves to.  Synchronous.
+ *   best_out  host [2], may be NULL: the chosen blocks_per_cu and variant (-1
+ *             for forms without variants)
+ *   ms_out    host [3*max_blocks_per_cu], may be NULL: time of candidate
+ *             (variant v, blocks b) at [v*max_blocks_per_cu + b - 1] (streamed
+ *             form), or at [b - 1] (other forms); -1 where not run
  * Scratch outputs are allocated and freed inside the call. */
 lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, const lpdec_params *p,
                             int32_t max_blocks_per_cu, int32_t *best_out, float *ms_out, void *stream);

@@ -61,7 +61,7 @@ class _LaunchInfo(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("threads", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
                 ("vgprs", ctypes.c_int32), ("runtime_blocks_per_cu", ctypes.c_int32),
                 ("resource_blocks_per_cu", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("register_chunks", ctypes.c_int32)]
+                ("variant", ctypes.c_int32)]
 
 
 class _ServerConfig(ctypes.Structure):
@@ -220,13 +220,13 @@ class Code:
         _check(_lib.lpdec_code_launch_info(self.handle, ctypes.byref(p), ctypes.byref(li)))
         return {k: getattr(li, k) for k, _ in _LaunchInfo._fields_}
 
-    def set_tuning(self, mode: int, blocks_per_cu: int = 0, register_chunks: int = -1):
-        _check(_lib.lpdec_code_set_tuning(self.handle, int(mode), int(blocks_per_cu), int(register_chunks)))
+    def set_tuning(self, mode: int, blocks_per_cu: int = 0, variant: int = -1):
+        _check(_lib.lpdec_code_set_tuning(self.handle, int(mode), int(blocks_per_cu), int(variant)))
 
     def autotune(self, llr, max_blocks_per_cu: int = 4, stream=None, **params):
         """Time decodes of the sample batch llr (float32 [B, n] CUDA tensor) over the
-        launch candidates and keep the fastest.  Returns ((blocks_per_cu,
-        register_chunks), {(register_chunks, blocks_per_cu): ms})."""
+        launch candidates and keep the fastest.  Returns ((blocks_per_cu, variant),
+        {(variant, blocks_per_cu): ms})."""
         torch = _torch()
         B = int(llr.shape[0]) if llr.dim() == 2 else 1
         if llr.numel() != B * self.n:
@@ -234,14 +234,15 @@ class Code:
         p = _params(**params)
         mb = int(max_blocks_per_cu)
         best = (ctypes.c_int32 * 2)()
-        ms = (ctypes.c_float * (2 * mb))()
+        ms = (ctypes.c_float * (3 * mb))()
         _check(_lib.lpdec_autotune(self.handle, B, _dev_ptr(llr, torch.float32, "llr"), ctypes.byref(p),
                                    mb, best, ms, _stream(stream)))
+        streamed = self.launch_info(**params)["mode"] == MODE_STREAMED
         times = {}
-        for v in range(2):
+        for v in range(3 if streamed else 1):
             for b in range(mb):
                 if ms[v * mb + b] >= 0:
-                    times[(-1 if v == 0 else 0, b + 1)] = float(ms[v * mb + b])
+                    times[(v if streamed else -1, b + 1)] = float(ms[v * mb + b])
         return (best[0], best[1]), times
 
     def close(self):

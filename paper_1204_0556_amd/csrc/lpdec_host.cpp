@@ -318,10 +318,24 @@ void persistent_global_config(const Shape &s, LaunchConfig *cfg) {
     cfg->state_stride = s.Eint_max;
 }
 
-void streamed_config(const Shape &s, bool half, LaunchConfig *cfg) {
+// Streamed variants (tuning value): 0 re-reads each chunk's z, u from HBM in every
+// phase; 1 keeps two chunks per wave in registers, two workgroups per CU; 2 as 1
+// with one workgroup per CU staging the next frame in LDS by direct-to-LDS loads
+// (chosen only on request or by the autotuner).  Default: 1 when the code allows
+// it, else 0.
+void streamed_config(const Shape &s, bool half, LaunchConfig *cfg, int variant = -1) {
     cfg->form = Form::Streamed;
     cfg->slot_mode = slot_mode_for(s, &cfg->lds_bytes);
     cfg->cpt_tmpl = (cfg->slot_mode == 1 && s.cpt <= 2 && s.dclass == 0) ? 2 : 0;
+    const int threads = s.waves * kWave;
+    // staged: all LDS static (z, u, slots of kStageEdges; gamma/mu, x of kStageVars)
+    const size_t stage_lds = sizeof(float) * (3 * (size_t)kStageEdges + 2 * kStageVars);
+    const bool stage_ok = cfg->cpt_tmpl == 2 && !half && threads <= 768 && s.dv > 0 &&
+                          s.Eint_max <= kStageEdges && s.Emax <= kStageEdges && s.nmax <= kStageVars &&
+                          s.nmax <= 4 * threads && stage_lds + kStaticLds <= kLdsLimit;
+    if (variant == 0) cfg->cpt_tmpl = 0;
+    cfg->staged = stage_ok && variant == 2;
+    if (cfg->staged) cfg->lds_bytes = 0;
     cfg->dclass = s.dclass;
     cfg->vpt_tmpl = 0;
     cfg->dv = 0;
@@ -383,9 +397,8 @@ lpdec_status resolve_config(const Shape &s, const lpdec_params &p, bool scattere
     if (mode == LPDEC_MODE_STREAMED) {
         if (scattered)
             return fail(LPDEC_EUNSUPPORTED, "the streamed form decodes one dense batch of one code per call");
-        streamed_config(s, half, cfg);
-        const int ch = code ? code->tune_chunks[static_cast<int>(Form::Streamed)] : -1;
-        if (ch == 0) cfg->cpt_tmpl = 0;
+        streamed_config(s, half, cfg, code ? code->tune_variant[static_cast<int>(Form::Streamed)] : -1);
+        (void)code;
     }
     return LPDEC_OK;
 }
@@ -686,19 +699,18 @@ lpdec_status lpdec_code_launch_info(const lpdec_code *code, const lpdec_params *
     out->runtime_blocks_per_cu = q.occupancy;
     out->resource_blocks_per_cu = resource_blocks_per_cu(cfg, q);
     out->blocks_per_cu = blocks_per_cu(cfg, code);
-    out->register_chunks = cfg.cpt_tmpl;
+    out->variant = cfg.form != Form::Streamed ? -1 : (cfg.cpt_tmpl == 0 ? 0 : (cfg.staged ? 2 : 1));
     return LPDEC_OK;
 }
 
-lpdec_status lpdec_code_set_tuning(lpdec_code *code, int32_t mode, int32_t bpc, int32_t chunks) {
+lpdec_status lpdec_code_set_tuning(lpdec_code *code, int32_t mode, int32_t bpc, int32_t variant) {
     if (!code) return fail(LPDEC_EINVAL, "code must not be NULL");
     const int f = form_of_mode(mode);
     if (f < 0) return fail(LPDEC_EINVAL, "mode must be RESIDENT, STREAMED or PERSISTENT_GLOBAL (got %d)", mode);
     if (bpc < 0 || bpc > 32) return fail(LPDEC_EINVAL, "blocks_per_cu must lie in 0..32 (got %d)", bpc);
-    if (chunks != -1 && chunks != 0 && chunks != 2)
-        return fail(LPDEC_EINVAL, "register_chunks must be -1, 0 or 2 (got %d)", chunks);
+    if (variant < -1 || variant > 2) return fail(LPDEC_EINVAL, "variant must lie in -1..2 (got %d)", variant);
     code->tune_bpc[f] = bpc;
-    code->tune_chunks[f] = chunks;
+    code->tune_variant[f] = variant;
     return LPDEC_OK;
 }
 
@@ -715,18 +727,18 @@ lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, c
     st = resolve_config(shape_of(&one, 1), p, false, &cfg, nullptr);
     if (st != LPDEC_OK) return st;
     const int f = static_cast<int>(cfg.form);
-    const int nvar = (cfg.form == Form::Streamed && cfg.cpt_tmpl > 0) ? 2 : 1;
+    const int nvar = cfg.form == Form::Streamed ? 3 : 1;
     hipStream_t stream = static_cast<hipStream_t>(stream_v);
     const size_t n = (size_t)code->dc.n;
     float *x = nullptr;
     int32_t *it = nullptr;
     uint8_t *fl = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const int saved = code->tune_bpc[f], saved_ch = code->tune_chunks[f];
-    int best = 0, best_ch = -1;
+    const int saved = code->tune_bpc[f], saved_var = code->tune_variant[f];
+    int best = 0, best_var = -1;
     float best_ms = 0.0f;
     if (ms_out)
-        for (int k = 0; k < 2 * max_bpc; ++k) ms_out[k] = -1.0f;
+        for (int k = 0; k < 3 * max_bpc; ++k) ms_out[k] = -1.0f;
     auto run = [&]() -> lpdec_status {
         HIP_TRY(hipMalloc(&x, sizeof(float) * n * batch));
         HIP_TRY(hipMalloc(&it, sizeof(int32_t) * batch));
@@ -734,8 +746,14 @@ lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, c
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
         for (int v = 0; v < nvar; ++v) {
-            const int ch = v == 0 ? -1 : 0;
-            code->tune_chunks[f] = ch;
+            const int var = nvar == 1 ? -1 : v;
+            code->tune_variant[f] = var;
+            if (nvar > 1) {  // a streamed variant the code does not allow falls back: skip it
+                LaunchConfig probe{};
+                streamed_config(shape_of(&one, 1), p.storage == LPDEC_STORAGE_FP16, &probe, var);
+                const int got = probe.cpt_tmpl == 0 ? 0 : (probe.staged ? 2 : 1);
+                if (got != var) continue;
+            }
             for (int b = 0; b <= max_bpc; ++b) {
                 code->tune_bpc[f] = b == 0 ? 1 : b;  // b = 0: untimed warm-up
                 HIP_TRY(hipEventRecord(e0, stream));
@@ -748,7 +766,7 @@ lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, c
                 HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
                 if (b == 0) continue;
                 if (ms_out) ms_out[v * max_bpc + b - 1] = ms;
-                if (best == 0 || ms < best_ms) { best = b; best_ch = ch; best_ms = ms; }
+                if (best == 0 || ms < best_ms) { best = b; best_var = var; best_ms = ms; }
             }
         }
         return LPDEC_OK;
@@ -761,14 +779,14 @@ lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, c
     if (e1) (void)hipEventDestroy(e1);
     if (st != LPDEC_OK) {
         code->tune_bpc[f] = saved;
-        code->tune_chunks[f] = saved_ch;
+        code->tune_variant[f] = saved_var;
         return st;
     }
     code->tune_bpc[f] = best;
-    code->tune_chunks[f] = best_ch;
+    code->tune_variant[f] = best_var;
     if (best_out) {
         best_out[0] = best;
-        best_out[1] = best_ch;
+        best_out[1] = best_var;
     }
     return LPDEC_OK;
 }

@@ -10,6 +10,9 @@ namespace lpdec {
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxThreads = 1024;  // workgroup limit
 constexpr int kMaxWaves = kMaxThreads / kWave;
+// LDS staging of the streamed form: one frame's z, u (edges) and gamma/mu (variables)
+constexpr int kStageEdges = 8192;
+constexpr int kStageVars = 4096;
 constexpr int kMaxD = 8;           // LPDEC_MAX_CHECK_DEGREE
 
 // Device view of one code (all pointers are device memory owned by the code).
@@ -106,6 +109,7 @@ struct LaunchConfig {
     int dv;            // every variable has this degree (0: mixed), resident form
     int slot_mode;     // 0 global float slots, 1 LDS float slots, 2 LDS fixed-point accumulators
     bool half;         // fp16 state storage (streamed only)
+    bool staged;       // streamed: next frame's state staged in LDS by direct-to-LDS loads
     int threads;       // workgroup size
     int grid;          // workgroups
     size_t lds_bytes;  // dynamic LDS

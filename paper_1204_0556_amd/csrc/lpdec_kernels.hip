@@ -227,6 +227,28 @@ __device__ __forceinline__ void wg_barrier() {
     }
 }
 
+// Barrier for the LDS-staged streamed form: this wave's LDS operations complete,
+// then s_barrier.  Unlike a fenced barrier it does not wait for the direct-to-LDS
+// loads of the next frame's state, which stay in flight across the phases; the
+// "memory" clobber keeps the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void lds_barrier_nofence() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+// Wait for this wave's outstanding vector-memory operations.  A real s_waitcnt
+// (vmcnt 0; expcnt and lgkmcnt left at their maxima) rather than inline asm, so
+// the compiler's wait-count tracking knows that every earlier load has landed.
+__device__ __forceinline__ void vmem_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// Direct-to-LDS loads: lane l's 16 (4) bytes from src land at lds_base + 16 l (4 l);
+// lds_base must be the same in every lane of the wave.  (Kept out of lambdas: a
+// target builtin inside a lambda of a kernel template suppresses the kernel's
+// host-side launch stub.)
+__device__ __forceinline__ void lds_copy16(const float *src, float *lds_base) {
+    __builtin_amdgcn_global_load_lds(src, lds_base, 16, 0, 0);
+}
+__device__ __forceinline__ void lds_copy4(const float *src, float *lds_base) {
+    __builtin_amdgcn_global_load_lds(src, lds_base, 4, 0, 0);
+}
+
 template <int DMIN, int DMAX, typename F>
 __device__ __forceinline__ void dispatch_degree(int d, F &&f) {
     if constexpr (DMIN == DMAX) {
@@ -319,22 +341,39 @@ __device__ __forceinline__ void st_state(void *p, size_t i, float a) {
 // check l of each of them.  CPT > 0 keeps those chunks' z,u (and packed edge
 // metadata) in registers; CPT == 0 walks the chunks and re-reads state.
 // Variable side: thread t owns internal variables t, t + NT, ...
-// Streamed form with register-held chunks: the register budget is capped so
-// that two workgroups of <= 768 threads share a CU (6 waves per SIMD); one
-// workgroup's memory waits then overlap the other's arithmetic.
-template <int DMIN, int DMAX, int CPT, int VPT, bool RES, bool PERSIST, int SM, bool HALF, int MAXT, int DV>
-__global__ void __launch_bounds__(MAXT, (!PERSIST && CPT > 0) ? (MAXT <= 768 ? 6 : 4) : 1)
+// Streamed form with register-held chunks: either the register budget is capped
+// so that two workgroups of <= 768 threads share a CU (6 waves per SIMD) and one
+// workgroup's memory waits overlap the other's arithmetic, or (STG) one
+// workgroup per CU stages the next frame's z, u and gamma/mu into LDS with
+// direct-to-LDS loads issued right after the current frame's state has been
+// read, so the loads stream in during the current frame's three phases.
+template <int DMIN, int DMAX, int CPT, int VPT, bool RES, bool PERSIST, int SM, bool HALF, int MAXT, int DV,
+          bool STG>
+__global__ void __launch_bounds__(MAXT, (!PERSIST && CPT > 0 && !STG) ? (MAXT <= 768 ? 6 : 4) : 1)
 k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateIO sio, StreamArgs sa,
          int lds_E, int slot_stride, int state_stride) {
     // SM: where the slot exchange lives -- 0 global float slots, 1 LDS float slots,
     // 2 LDS fixed-point accumulators (x then sits in each entry's high word)
     static_assert(!RES || (CPT > 0 && PERSIST && SM == 1), "register-resident form needs CPT>0");
     static_assert(SM != 2 || CPT == 0, "accumulator mode walks chunks");
+    static_assert(!STG || (!PERSIST && CPT > 0 && SM == 1 && !HALF && DMIN == 6 && DMAX == 6 && VPT == 0),
+                  "LDS staging: streamed FP32 degree-6 form with register-held chunks");
     constexpr bool LDS_SLOTS = SM == 1;
     constexpr int XS = (SM == 2) ? 2 : 1;
     extern __shared__ __attribute__((aligned(16))) float lds[];  // 64-bit accumulators need 8-byte alignment
     __shared__ float s_red[2][2][kMaxWaves];
     __shared__ int s_frame;
+    // LDS staging of one frame (STG): z and u in the lane-minor edge order, gamma/mu
+    // in internal variable order
+    constexpr int SE = STG ? kStageEdges : 1;
+    constexpr int SN = STG ? kStageVars : 1;
+    __shared__ __attribute__((aligned(16))) float stg_z[SE];
+    __shared__ __attribute__((aligned(16))) float stg_u[SE];
+    __shared__ __attribute__((aligned(16))) float stg_g[SN];
+    // STG: slots and x in static LDS as well, so that every LDS array is a distinct
+    // object and the compiler can tell the staging area's loads from phase traffic
+    __shared__ __attribute__((aligned(16))) float stg_slots[SE];
+    __shared__ __attribute__((aligned(16))) float stg_x[SN];
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -342,13 +381,15 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
     const int NT = blockDim.x;
     const int NW = NT >> 6;
 
-    float *slots = LDS_SLOTS ? lds : (sa.gslots + (size_t)blockIdx.x * slot_stride);
-    float *xs = (SM == 1) ? (lds + lds_E) : ((SM == 2) ? lds + 1 : lds);
+    float *slots = STG ? stg_slots : (LDS_SLOTS ? lds : (sa.gslots + (size_t)blockIdx.x * slot_stride));
+    float *xs = STG ? stg_x : ((SM == 1) ? (lds + lds_E) : ((SM == 2) ? lds + 1 : lds));
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(lds);
     unsigned *xprev = sa.gxprev ? sa.gxprev + (size_t)blockIdx.x * sa.gmu_stride : nullptr;
 
     constexpr int NC = CPT > 0 ? CPT : 1;
     float z[NC][DMAX], u[NC][DMAX];
+    constexpr int GQ = STG ? 4 : 1;  // STG: gamma/mu of this thread's variables tid + t NT
+    float gq[GQ];
     constexpr bool LBAR = SM != 0;  // phase barriers need only order LDS
     uint32_t meta[NC][DMAX];
     int cdeg[NC], coff[NC];
@@ -381,6 +422,27 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
     if constexpr (!PERSIST) {
         if (blockIdx.x == 0 && tid == 0) sa.active_count[(ip.launch + 1) & 1] = 0;  // next launch's counter
     }
+    // STG: start the direct-to-LDS copy of frame g's z, u (16 bytes per lane) and
+    // gamma/mu (4 bytes per lane); each wave copies every NW-th 1 KB block
+    auto stage_issue = [&](const DevCode &Cg, int g) {
+        if constexpr (STG) {
+            const float *zs = static_cast<const float *>(sa.z) + (size_t)g * Cg.E_int;
+            const float *us = static_cast<const float *>(sa.u) + (size_t)g * Cg.E_int;
+            for (int c = wave; c < (Cg.E_int + 255) >> 8; c += NW) {
+                const int idx = (c << 8) + (lane << 2);
+                if (idx < Cg.E_int) {  // E_int is a multiple of 64: idx + 3 < E_int too
+                    lds_copy16(zs + idx, stg_z + (c << 8));
+                    lds_copy16(us + idx, stg_u + (c << 8));
+                }
+            }
+            const float *gs = Cg.var_identity ? fb.llr + (int64_t)g * Cg.n : sa.gmu + (size_t)g * sa.gmu_stride;
+            for (int c = wave; c < (Cg.n + 63) >> 6; c += NW) {
+                const int i = (c << 6) + lane;
+                if (i < Cg.n) lds_copy4(gs + i, stg_g + (c << 6));
+            }
+        }
+    };
+    int pending = -1;  // STG: the next frame, its copy already issued
     for (;;) {
         int f;
         if constexpr (PERSIST) {
@@ -391,6 +453,16 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             __syncthreads();
             f = __builtin_amdgcn_readfirstlane(s_frame);
             __syncthreads();
+        } else if constexpr (STG) {
+            if (pending < 0) {
+                f = next_active();
+                if (f < fb.nframes) stage_issue(codes[0], f);
+            } else {
+                f = pending;
+            }
+            pending = -1;
+            vmem_wait_all();  // this wave's share of frame f's copy has landed
+            lds_barrier_nofence();
         } else {
             f = next_active();
         }
@@ -432,6 +504,9 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                     }
                 }
                 cur_code = ci;
+                // STG: the metadata must not be waited for again inside the frame
+                // loop, where such a wait would also stall on the staged loads
+                if constexpr (STG) vmem_wait_all();
             }
         }
 
@@ -530,7 +605,16 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             if constexpr (CPT > 0) {
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
-                    if constexpr (!RES) {
+                    if constexpr (STG) {
+#pragma unroll
+                        for (int e = 0; e < DMAX; ++e) {
+                            if (cval[k] && e < cdeg[k]) {
+                                const int p = coff[k] + e * kWave + lane;
+                                z[k][e] = stg_z[p];
+                                u[k][e] = stg_u[p];
+                            }
+                        }
+                    } else if constexpr (!RES) {
 #pragma unroll
                         for (int e = 0; e < DMAX; ++e) {
                             if (cval[k] && e < cdeg[k]) {
@@ -594,12 +678,35 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 // order, else from the copy staged in internal order
                 const float *gsrc = C.var_identity ? gam : gmu_row;
                 const float gscale = C.var_identity ? ip.mu_inv : 1.0f;
-                if (C.dv > 0) {  // kernel-uniform degree: a scalar loop
-                    for (int i = tid; i < C.n; i += NT) {
-                        const int b = C.dv * i;
-                        float acc = 0.0f;
-                        for (int p = 0; p < C.dv; ++p) acc += slots[b + p];
-                        xs[i] = clamp01((acc - gsrc[i] * gscale) * C.dv_inv);
+                if constexpr (STG) {  // gamma/mu taken from the staging area in phase A
+#pragma unroll
+                    for (int t = 0; t < GQ; ++t) {
+                        const int i = tid + t * NT;
+                        if (i < C.n) {
+                            const int b = C.dv * i;
+                            float acc = 0.0f;
+                            for (int p = 0; p < C.dv; ++p) acc += slots[b + p];
+                            xs[i] = clamp01((acc - gq[t]) * C.dv_inv);
+                        }
+                    }
+                } else if (C.dv > 0) {  // kernel-uniform degree: four variables per pass, loads first
+                    for (int i0 = tid; i0 < C.n; i0 += 4 * NT) {
+                        float g[4];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int i = i0 + t * NT;
+                            g[t] = (i < C.n) ? gsrc[i] : 0.0f;
+                        }
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int i = i0 + t * NT;
+                            if (i < C.n) {
+                                const int b = C.dv * i;
+                                float acc = 0.0f;
+                                for (int p = 0; p < C.dv; ++p) acc += slots[b + p];
+                                xs[i] = clamp01((acc - g[t] * gscale) * C.dv_inv);
+                            }
+                        }
                     }
                 } else {
                     for (int i = tid; i < C.n; i += NT) {
@@ -705,14 +812,32 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             }
         } else {
             const int it = iter0 + 1;
+            auto pbar = [&]() {
+                if constexpr (STG) lds_barrier_nofence();
+                else wg_barrier<LBAR>();
+            };
+            if constexpr (STG) {
+                const float gscale = C.var_identity ? ip.mu_inv : 1.0f;
+#pragma unroll
+                for (int t = 0; t < GQ; ++t) {
+                    const int i = tid + t * NT;
+                    gq[t] = (i < C.n) ? stg_g[i] * gscale : 0.0f;
+                }
+            }
             phase_a();
-            wg_barrier<LBAR>();
+            pbar();
+            if constexpr (STG) {
+                // every wave has read the staged frame: stage the next one
+                const int g = next_active();
+                pending = g;
+                if (g < fb.nframes) stage_issue(C, g);
+            }
             phase_b();
-            wg_barrier<LBAR>();
+            pbar();
             float rp = 0.0f, rd = 0.0f;
             phase_c(rp, rd);
             publish(0, rp, rd);
-            wg_barrier<LBAR>();
+            pbar();
             conv = converged(0);
             iters = it;
             const bool fin = __builtin_amdgcn_readfirstlane(conv || it >= ip.max_iter);
@@ -722,7 +847,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 else atomicAdd(sa.active_count + (ip.launch & 1), 1);
             }
             if (!fin) {
-                wg_barrier<LBAR>();  // LDS reuse by the next frame of this workgroup
+                pbar();  // LDS reuse by the next frame of this workgroup
                 continue;
             }
         }
@@ -852,11 +977,11 @@ hipError_t launch_stream_init(const DevCode *codes_dev, int nframes, const Launc
 // Instantiation table.
 
 template <int DMIN, int DMAX, int CPT, int VPT, bool RES, bool PERSIST, int SM, bool HALF, int MAXT = kMaxThreads,
-          int DV = 0>
+          int DV = 0, bool STG = false>
 static hipError_t go(const LaunchConfig &cfg, const DevCode *codes, const FrameBatch &fb, const IterParams &ip,
                      const StateIO &sio, const StreamArgs &sa, hipStream_t stream, KernelQuery *q) {
     if (cfg.threads > MAXT) return hipErrorInvalidConfiguration;
-    auto kern = k_decode<DMIN, DMAX, CPT, VPT, RES, PERSIST, SM, HALF, MAXT, DV>;
+    auto kern = k_decode<DMIN, DMAX, CPT, VPT, RES, PERSIST, SM, HALF, MAXT, DV, STG>;
     if (cfg.lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg.lds_bytes);
@@ -898,6 +1023,8 @@ static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const 
             if (cfg.slot_mode == 1) {
                 // register-held chunks: degree-6 codes only (DMAX = 8 register arrays spill)
                 if constexpr (DMIN == 6 && DMAX == 6) {
+                    if (cfg.staged && cfg.cpt_tmpl == 2 && cfg.threads <= 768 && !cfg.half)
+                        LPD_GO(2, 0, false, false, 1, false, 768, 0, true);
                     if (cfg.cpt_tmpl == 2 && cfg.threads <= 768 && !cfg.half) LPD_GO(2, 0, false, false, 1, false, 768);
                     if (cfg.cpt_tmpl == 2 && cfg.threads <= 768 && cfg.half) LPD_GO(2, 0, false, false, 1, true, 768);
                     if (cfg.cpt_tmpl == 2 && !cfg.half) LPD_GO(2, 0, false, false, 1, false);

@@ -84,7 +84,7 @@ struct lpdec_code {
     bool resident_ok = false;
     lpdec::LaunchConfig resident_cfg{};
     int tune_bpc[3] = {0, 0, 0};     // workgroups per CU by form (0: runtime estimate)
-    int tune_chunks[3] = {-1, -1, -1};  // register-held chunks per wave by form (-1: default)
+    int tune_variant[3] = {-1, -1, -1};  // kernel variant by form (streamed only; -1: default)
     Workspace ws;
     ~lpdec_code() {
         if (d_dc) (void)hipFree(d_dc);

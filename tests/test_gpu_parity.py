@@ -102,6 +102,24 @@ def test_forms_agree_bitwise():
         assert np.abs(o[0] - outs[0][0]).max() == 0.0
 
 
+def test_streamed_variants_many_frames_per_workgroup():
+    # 3072 frames at low SNR: every workgroup walks many frames, finished and
+    # unfinished ones interleave, and the staged variant's copy of the next frame
+    # overlaps the current one.  All streamed variants equal the resident form.
+    H = W.gallager36(2640)
+    llr = np.concatenate([W.awgn_batch(H, 1536, s, tag="variants") for s in (1.5, 2.5)])
+    code = lp.Code(H)
+    kw = dict(max_iter=120)
+    x0, it0, fl0 = (host(t) for t in lp.decode(code, dev(llr), mode=lp.MODE_RESIDENT, **kw))
+    for var in (2, 1, 0):
+        code.set_tuning(lp.MODE_STREAMED, 0, var)
+        print(f"streamed variant {var}: {llr.shape[0]} frames", flush=True)
+        assert code.launch_info(mode=lp.MODE_STREAMED)["variant"] == var
+        x, it, fl = (host(t) for t in lp.decode(code, dev(llr), mode=lp.MODE_STREAMED, **kw))
+        assert np.array_equal(it, it0) and np.array_equal(fl, fl0)
+        assert np.abs(x - x0).max() == 0.0
+
+
 def _compare_decodes(H, llr, x, it, fl, ref, max_iter):
     ambiguous = np.any(np.abs(ref.x - 0.5) < 1e-3, axis=1)
     hard, href = (x >= 0.5), (ref.x >= 0.5)

@@ -39,12 +39,14 @@ def test_results_do_not_depend_on_the_launch_shape(form):
     ref = _decode(code, llr, FORMS[form], **kw)
     shapes = [(1, -1), (2, -1), (3, -1)]
     if form == "streamed":
-        shapes += [(1, 0), (2, 0)]
-    for bpc, ch in shapes:
-        code.set_tuning(FORMS[form], bpc, ch)
+        shapes += [(1, 0), (2, 0), (1, 1), (2, 1), (1, 2), (2, 2)]
+    for bpc, var in shapes:
+        code.set_tuning(FORMS[form], bpc, var)
+        if form == "streamed" and var >= 0:
+            assert code.launch_info(mode=FORMS[form])["variant"] == var
         got = _decode(code, llr, FORMS[form], **kw)
         for a, b in zip(ref, got):
-            assert np.array_equal(a, b), (form, bpc, ch)
+            assert np.array_equal(a, b), (form, bpc, var)
     code.set_tuning(FORMS[form], 0, -1)
 
 
@@ -54,10 +56,11 @@ def test_autotune_keeps_results_and_records_choice():
     llr = torch.from_numpy(W.awgn_batch(H, 512, 2.0, tag="tune")).cuda()
     kw = dict(W.PAPER_PARAMS, max_iter=200)
     ref = _decode(code, llr, lp.MODE_STREAMED, **kw)
-    (bpc, ch), times = code.autotune(llr, max_blocks_per_cu=2, mode=lp.MODE_STREAMED, **kw)
-    assert 1 <= bpc <= 2 and ch in (-1, 0)
-    assert len(times) == 4 and all(t > 0 for t in times.values())
-    assert times[(ch, bpc)] == min(times.values())
+    (bpc, var), times = code.autotune(llr, max_blocks_per_cu=2, mode=lp.MODE_STREAMED, **kw)
+    assert 1 <= bpc <= 2 and var in (0, 1, 2)
+    assert len(times) == 6 and all(t > 0 for t in times.values())
+    assert times[(var, bpc)] == min(times.values())
+    assert code.launch_info(mode=lp.MODE_STREAMED)["variant"] == var
     assert code.launch_info(mode=lp.MODE_STREAMED)["blocks_per_cu"] == bpc
     got = _decode(code, llr, lp.MODE_STREAMED, **kw)
     for a, b in zip(ref, got):
@@ -72,3 +75,4 @@ def test_tuning_rejects_bad_values():
         code.set_tuning(lp.MODE_RESIDENT, 33, -1)
     with pytest.raises(lp.LpdecError):
         code.set_tuning(lp.MODE_STREAMED, 1, 3)
+    code.set_tuning(lp.MODE_STREAMED, 1, 2)  # n = 96: staging allowed, default already
