@@ -624,9 +624,11 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                             }
                         }
                     }
+                    if (cval[k]) {  // one lane mask per chunk; all-degree-6 codes need no per-edge test
 #pragma unroll
-                    for (int e = 0; e < DMAX; ++e)
-                        if (cval[k] && e < cdeg[k]) slots[meta[k][e] >> 16] = z[k][e] - u[k][e];
+                        for (int e = 0; e < DMAX; ++e)
+                            if (DMIN == DMAX || e < cdeg[k]) slots[meta[k][e] >> 16] = z[k][e] - u[k][e];
+                    }
                 }
             } else {
                 for (int c = wave; c < C.nchunks && wave < C.waves; c += C.waves) {
@@ -786,14 +788,13 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         int iters;
         bool conv = false;
         if constexpr (PERSIST) {
+            // iteration it = B, C, then the next iteration's A; the stopping test
+            // for it reads the residuals published by C after the barrier that
+            // follows that A, so it costs no barrier of its own
             int it = 1;
+            phase_a();
+            wg_barrier<LBAR>();
             for (;; ++it) {
-                phase_a();
-                wg_barrier<LBAR>();
-                if (it > 1) {
-                    if (__builtin_amdgcn_readfirstlane(converged((it - 1) & 1))) { conv = true; break; }
-                    if (it > ip.max_iter) break;
-                }
                 phase_b();
                 wg_barrier<LBAR>();
                 float rp = 0.0f, rd = 0.0f;
@@ -802,8 +803,12 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 // accumulator mode: the next phase A adds into the entries that
                 // phase C is still reading x from
                 if constexpr (SM == 2) wg_barrier<LBAR>();
+                phase_a();
+                wg_barrier<LBAR>();
+                if (__builtin_amdgcn_readfirstlane(converged(it & 1))) { conv = true; break; }
+                if (it >= ip.max_iter) break;
             }
-            iters = conv ? it - 1 : ip.max_iter;
+            iters = conv ? it : ip.max_iter;
             if constexpr (SM == 2) {
                 // The stopping test ran after the next iteration's phase A, which
                 // accumulated into the entries holding x: restore the last x.
