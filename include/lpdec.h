@@ -251,7 +251,9 @@ lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, c
 
 /* The check-node operation alone: z_k = Pi_PPd(v_k) for `count` vectors of
  * degree d (2 <= d <= LPDEC_MAX_CHECK_DEGREE), Algorithm 2 / Sec. 4.4.
- *   v, z  device [count*d] FP32, row-major (z may not alias v). */
+ *   v, z  device [count*d] FP32, row-major (z may not alias v).  Entries of v
+ *         must be finite; the result for a vector holding a NaN or an infinity
+ *         is unspecified. */
 lpdec_status lpdec_project(int32_t d, int32_t count, const float *v, float *z, void *stream);
 
 /* ------------------------------------------------------------------------- */

@@ -34,4 +34,7 @@ struct EvalBatch {
 
 hipError_t launch_evaluate(const DevCode *codes, const EvalBatch &eb, int nmax, hipStream_t stream);
 
+// flags_out[f] = 0x80 for frames with a non-finite LLR, else 0 (run before a decode)
+hipError_t launch_check_finite(const DevCode *codes, const FrameBatch &fb, hipStream_t stream);
+
 }  // namespace lpdec

@@ -288,6 +288,27 @@ __global__ void __launch_bounds__(256) k_evaluate(const DevCode *__restrict__ co
     }
 }
 
+// ---------------------------------------------------------------------------
+// Input check before a decode: flags_out[f] = 0x80 when frame f holds a
+// non-finite LLR (tested on the bit pattern), else 0.  The decoder kernels are
+// built without NaN semantics and take their invalid-frame decision from here.
+__global__ void __launch_bounds__(256) k_check_finite(const DevCode *__restrict__ codes, FrameBatch fb) {
+    const int f = blockIdx.x;
+    if (f >= fb.nframes) return;
+    const DevCode &C = codes[fb.code_of_frame ? fb.code_of_frame[f] : 0];
+    const int64_t lo = fb.llr_off ? fb.llr_off[f] : (int64_t)f * C.n;
+    bool bad = false;
+    for (int i = threadIdx.x; i < C.n; i += blockDim.x) bad |= !finite_f(fb.llr[lo + i]);
+    const int any = __syncthreads_or(bad);
+    if (threadIdx.x == 0) fb.flags_out[f] = any ? 0x80 : 0;
+}
+
+hipError_t launch_check_finite(const DevCode *codes, const FrameBatch &fb, hipStream_t stream) {
+    if (fb.nframes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_finite, dim3(fb.nframes), dim3(256), 0, stream, codes, fb);
+    return hipGetLastError();
+}
+
 hipError_t launch_evaluate(const DevCode *codes, const EvalBatch &eb, int nmax, hipStream_t stream) {
     if (eb.nframes <= 0) return hipSuccess;
     const size_t lds = ((size_t)nmax + 15) / 16 * 16;

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/lpdec.h"
+#include "lpdec_aux.h"
 #include "lpdec_internal.h"
 #include "lpdec_runtime.h"
 
@@ -495,6 +496,11 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
         fb.llr_off = reinterpret_cast<const int64_t *>(d + tbl_bytes);
         fb.x_off = fb.llr_off + nframes;
         if (code_of_frame) fb.code_of_frame = reinterpret_cast<const int32_t *>(fb.x_off + nframes);
+    }
+    // invalid-input flags for every frame, read by the decode kernels
+    {
+        hipError_t e = launch_check_finite(codes_dev, fb, stream);
+        if (e != hipSuccess) return fail(LPDEC_EDEVICE, "input check launch failed: %s", hipGetErrorString(e));
     }
     IterParams ip{};
     ip.mu_inv = 1.0f / p.mu;

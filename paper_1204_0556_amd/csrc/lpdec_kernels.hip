@@ -30,8 +30,11 @@ namespace lpdec {
 
 __device__ __forceinline__ float clamp01(float a) { return __builtin_amdgcn_fmed3f(a, 0.0f, 1.0f); }
 
-__device__ __forceinline__ bool finite_bits(float a) {
-    return (__float_as_uint(a) & 0x7f800000u) != 0x7f800000u;
+// Frames with a non-finite LLR are found before the decode by k_check_finite
+// (lpdec_aux.hip, compiled with NaN semantics), which marks them 0x80 in flags_out;
+// this file is compiled with -fno-honor-nans and never tests for NaN itself.
+__device__ __forceinline__ bool frame_invalid(const FrameBatch &fb, int f) {
+    return (__builtin_amdgcn_readfirstlane(fb.flags_out[f]) & 0x80) != 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -511,25 +514,22 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         }
 
         // -- frame set-up: gamma/mu, invalid-input check ----------------------
-        bool bad = false;
         if constexpr (VPT > 0) {
 #pragma unroll
             for (int t = 0; t < VPT; ++t) {
                 const int i = tid + t * NT;
                 float g = 0.0f;
-                if (i < C.n) {
-                    g = gam[C.var_identity ? i : C.var_orig[i]];
-                    bad |= !finite_bits(g);
-                }
+                if (i < C.n) g = gam[C.var_identity ? i : C.var_orig[i]];
                 vg[t] = g * ip.mu_inv;
             }
         } else if constexpr (PERSIST) {
-            for (int i = tid; i < C.n; i += NT) bad |= !finite_bits(gam[i]);
-            if (!C.var_identity)
+            if (!C.var_identity) {
                 for (int i = tid; i < C.n; i += NT) gmu_row[i] = gam[C.var_orig[i]] * ip.mu_inv;
+                __syncthreads();  // global staging, read by other threads in phase B
+            }
         }
         if constexpr (PERSIST) {
-            if (__builtin_amdgcn_readfirstlane(__syncthreads_or(bad))) {
+            if (frame_invalid(fb, f)) {
                 for (int i = tid; i < C.n; i += NT)
                     fb.x_out[(fb.x_off ? fb.x_off[f] : (int64_t)f * C.n) + i] = 0.5f;
                 __syncthreads();
@@ -933,9 +933,7 @@ k_stream_init(const DevCode *__restrict__ codes, FrameBatch fb, StateIO sio, Str
     const int ci = fb.code_of_frame ? fb.code_of_frame[f] : 0;
     const DevCode &C = codes[ci];
     const int64_t loff = fb.llr_off ? fb.llr_off[f] : (int64_t)f * C.n;
-    bool bad = false;
-    for (int i = threadIdx.x; i < C.n; i += blockDim.x) bad |= !finite_bits(fb.llr[loff + i]);
-    const int any_bad = __syncthreads_or(bad);
+    const int any_bad = frame_invalid(fb, f);
     const size_t base = (size_t)f * C.E_int;
     for (int p = threadIdx.x; p < C.E_int; p += blockDim.x) {
         float z0 = 0.0f, u0 = 0.0f;
