@@ -281,7 +281,7 @@ bool resident_config(const Shape &s, LaunchConfig *cfg) {
     const size_t lds = 4 * ((size_t)s.Emax + s.nmax);
     if (lds + kStaticLds > kLdsLimit) return false;
     cfg->form = Form::Resident;
-    cfg->cpt_tmpl = 2;
+    cfg->cpt_tmpl = (s.cpt <= 1 && vpt <= 4) ? 1 : 2;
     cfg->vpt_tmpl = vpt <= 4 ? 4 : 8;
     cfg->dclass = 0;
     cfg->dv = (s.dv == 3) ? 3 : 0;

@@ -1012,6 +1012,10 @@ static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const 
         case Form::Resident:
             // register budget: degree-6 codes only (the host never selects it otherwise)
             if constexpr (DMIN == 6 && DMAX == 6) {
+                // one chunk per wave (codes with m <= 1024): fewer registers, more
+                // workgroups per CU
+                if (cfg.cpt_tmpl == 1 && cfg.vpt_tmpl == 4 && cfg.dv == 3) LPD_GO(1, 4, true, true, 1, false, 768, 3);
+                if (cfg.cpt_tmpl == 1 && cfg.vpt_tmpl == 4) LPD_GO(1, 4, true, true, 1, false, 768);
                 if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4 && cfg.dv == 3) LPD_GO(2, 4, true, true, 1, false, 768, 3);
                 if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8 && cfg.dv == 3) LPD_GO(2, 8, true, true, 1, false, 768, 3);
                 if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4) LPD_GO(2, 4, true, true, 1, false, 768);
