@@ -68,6 +68,10 @@ def _create(lib, m, n, row_ptr, col_idx):
     ("bad row_ptr end", 1, 3, [0, 2], [0, 1, 2], EINVAL, "nnz"),
     ("degree above max", 1, 9, [0, 9], list(range(9)), EUNSUPPORTED, "degree 9"),
     ("no rows", 0, 3, [0], [0], EINVAL, "m and n"),
+    # size limits: 16-bit variable and slot indices in the edge metadata
+    ("n too large", 1, 65537, [0, 2], [0, 1], EUNSUPPORTED, "n > 65536"),
+    ("nnz too large", 8193, 65536, list(range(0, 65537, 8)) + [65544], list(range(65536)) + list(range(8)),
+     EUNSUPPORTED, "nnz > 65536"),
 ])
 def test_code_create_rejects(lib, case, m, n, rp, ci, status, msg):
     st, h, err = _create(lib, m, n, rp, ci)

@@ -127,3 +127,23 @@ def test_fp16_storage_error_is_bounded():
     x16, it16, fl16 = lp.decode(code, dev(llr), mode=lp.MODE_STREAMED, storage=lp.STORAGE_FP16)
     agree = np.all((host(x32) >= 0.5) == (host(x16) >= 0.5), axis=1)
     assert agree.mean() >= 0.99
+
+
+def test_largest_codes_use_global_slots():
+    # (3,6) n = 21840 has nnz = 65520, just under the 16-bit index limit; 8 n bytes
+    # of accumulators exceed the LDS, so the slot exchange lives in global memory.
+    H = W.gallager_regular(21840, 3, 6, seed=3)
+    assert H.nnz == 65520
+    llr = W.awgn_batch(H, 3, 2.5, tag="largest")
+    code = lp.Code(H)
+    ref = oracle.decode(H, llr, max_iter=15, tol=0.0, state=True)
+    outs = []
+    for m in (lp.MODE_PERSISTENT_GLOBAL, lp.MODE_STREAMED):
+        print(f"largest code n={H.n} mode={m}", flush=True)
+        x, it, fl, z, u = lp.decode_state(code, dev(llr), mode=m, max_iter=15, tol=0.0)
+        x, z, u = host(x), host(z), host(u)
+        assert np.abs(x - ref.x).max() <= 1e-4
+        assert np.abs(z - ref.z).max() <= 1e-4 and np.abs(u - ref.u).max() <= 1e-4
+        outs.append((x, z, u))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
