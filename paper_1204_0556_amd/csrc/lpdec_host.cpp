@@ -206,8 +206,16 @@ lpdec_status build_plan(int32_t m, int32_t n, int64_t nnz, const int32_t *row_pt
     }
     D.nchunks = (int)chunk_deg.size();
     D.E_int = (int)meta.size();
-    // waves: as many as possible up to 16 per workgroup (fewer chunks per wave)
-    D.cpt = (D.nchunks + kMaxWaves - 1) / kMaxWaves;
+    // waves: as many as possible up to 16 per workgroup (fewer chunks per wave),
+    // except for codes with checks of degree 7..8 (all >= 6) that the resident
+    // form can hold: those get at most 8 waves, so that up to 8 chunks per wave
+    // fit in the 256 registers a wave has at 2 waves per SIMD (at 16 waves a
+    // wave has 128, too few for 4 degree-8 chunks).  Every form of a code uses
+    // the same plan, so the forms stay bitwise identical.
+    const bool wide = dmin >= 6 && dmax > 6 && dmax <= 8 && D.nchunks <= 8 * 8 &&
+                      4 * ((size_t)nnz + n) + 1024 <= 160 * 1024;
+    const int max_waves = wide ? 8 : kMaxWaves;
+    D.cpt = (D.nchunks + max_waves - 1) / max_waves;
     D.waves = (D.nchunks + D.cpt - 1) / D.cpt;
 
     int *d_cdeg, *d_coff, *d_ccnt, *d_ecsr, *d_vorig;
@@ -248,7 +256,7 @@ struct Shape {
 
 Shape shape_of(const lpdec_code *const *codes, int ncodes) {
     Shape s;
-    bool all6 = true;
+    bool all6 = true, in68 = true;
     for (int c = 0; c < ncodes; ++c) {
         const DevCode &D = codes[c]->dc;
         s.waves = std::max(s.waves, D.waves);
@@ -257,9 +265,10 @@ Shape shape_of(const lpdec_code *const *codes, int ncodes) {
         s.Emax = std::max(s.Emax, D.E);
         s.Eint_max = std::max(s.Eint_max, D.E_int);
         all6 = all6 && D.dmin == 6 && D.dmax == 6;
+        in68 = in68 && D.dmin >= 6 && D.dmax <= 8;
         s.permuted = s.permuted || !D.var_identity;
     }
-    s.dclass = all6 ? 0 : 1;
+    s.dclass = all6 ? 0 : (in68 ? 2 : 1);
     s.dv = (codes[0]->dc.nvc == 1) ? codes[0]->dc.vc_deg[0] : 0;
     for (int c = 1; c < ncodes; ++c)
         if (codes[c]->dc.nvc != 1 || codes[c]->dc.vc_deg[0] != s.dv) s.dv = 0;
@@ -269,9 +278,31 @@ Shape shape_of(const lpdec_code *const *codes, int ncodes) {
 constexpr size_t kStaticLds = 1024;  // s_red + s_frame + alignment
 constexpr size_t kLdsLimit = 160 * 1024;
 
-// Resident form: z,u in registers (cpt <= 2 chunks per wave, DMAX = 6) and
-// gamma/mu of <= 8 variables per thread; slots and x in LDS.
+// Resident form: z,u in registers, slots and x in LDS.  Degree-6 codes: cpt <= 2
+// chunks per wave with their metadata, gamma/mu of <= 8 variables per thread,
+// <= 768 threads.  Check degrees 6..8: cpt <= 8 chunks per wave, metadata and
+// variable tables read from memory.
 bool resident_config(const Shape &s, LaunchConfig *cfg) {
+    if (s.dclass == 2) {
+        // threads per template: cpt 1-2 up to 1024, cpt 4 up to 768, cpt 8 up to 512
+        const int max_waves = s.cpt <= 2 ? kMaxWaves : (s.cpt <= 4 ? 12 : 8);
+        if (s.cpt > 8 || s.waves > max_waves) return false;
+        const size_t lds = 4 * ((size_t)s.Emax + s.nmax);
+        if (lds + kStaticLds > kLdsLimit) return false;
+        cfg->form = Form::Resident;
+        cfg->cpt_tmpl = s.cpt <= 1 ? 1 : (s.cpt <= 2 ? 2 : (s.cpt <= 4 ? 4 : 8));
+        cfg->vpt_tmpl = 0;
+        cfg->dclass = 2;
+        cfg->dv = 0;
+        cfg->slot_mode = 1;
+        cfg->half = false;
+        cfg->threads = s.waves * kWave;
+        cfg->lds_bytes = lds;
+        cfg->lds_E = s.Emax;
+        cfg->slot_stride = 0;
+        cfg->state_stride = 0;
+        return true;
+    }
     if (s.dclass != 0) return false;  // register budget only holds for degree-6 codes
     if (s.cpt > 2) return false;
     const int threads = s.waves * kWave;
@@ -309,7 +340,7 @@ void persistent_global_config(const Shape &s, LaunchConfig *cfg) {
     cfg->form = Form::PersistentGlobal;
     cfg->cpt_tmpl = 0;
     cfg->vpt_tmpl = 0;
-    cfg->dclass = s.dclass;
+    cfg->dclass = s.dclass == 0 ? 0 : 1;
     cfg->dv = 0;
     cfg->slot_mode = slot_mode_for(s, &cfg->lds_bytes);
     cfg->half = false;
@@ -328,6 +359,7 @@ void streamed_config(const Shape &s, bool half, LaunchConfig *cfg, int variant =
     cfg->form = Form::Streamed;
     cfg->slot_mode = slot_mode_for(s, &cfg->lds_bytes);
     cfg->cpt_tmpl = (cfg->slot_mode == 1 && s.cpt <= 2 && s.dclass == 0) ? 2 : 0;
+    cfg->dclass = s.dclass == 0 ? 0 : 1;
     const int threads = s.waves * kWave;
     // staged: all LDS static (z, u, slots of kStageEdges; gamma/mu, x of kStageVars)
     const size_t stage_lds = sizeof(float) * (3 * (size_t)kStageEdges + 2 * kStageVars);
@@ -337,7 +369,6 @@ void streamed_config(const Shape &s, bool half, LaunchConfig *cfg, int variant =
     if (variant == 0) cfg->cpt_tmpl = 0;
     cfg->staged = stage_ok && variant == 2;
     if (cfg->staged) cfg->lds_bytes = 0;
-    cfg->dclass = s.dclass;
     cfg->vpt_tmpl = 0;
     cfg->dv = 0;
     cfg->half = half;
@@ -523,12 +554,12 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
         HIP_TRY(ws.queue.ensure(sizeof(int)));
         fb.queue = static_cast<int *>(ws.queue.p);
         HIP_TRY(launch_fill_i32(fb.queue, 0, 1, stream));
+        if (s.permuted && cfg.vpt_tmpl == 0) {  // gamma/mu staged in internal variable order
+            HIP_TRY(ws.gmu.ensure(sizeof(float) * (size_t)cfg.grid * s.nmax));
+            sa.gmu = static_cast<float *>(ws.gmu.p);
+            sa.gmu_stride = s.nmax;
+        }
         if (cfg.form == Form::PersistentGlobal) {
-            if (s.permuted) {
-                HIP_TRY(ws.gmu.ensure(sizeof(float) * (size_t)cfg.grid * s.nmax));
-                sa.gmu = static_cast<float *>(ws.gmu.p);
-                sa.gmu_stride = s.nmax;
-            }
             HIP_TRY(ws.gstate.ensure(2 * sizeof(float) * (size_t)cfg.grid * cfg.state_stride));
             sa.z = ws.gstate.p;
             sa.u = static_cast<float *>(ws.gstate.p) + (size_t)cfg.grid * cfg.state_stride;

@@ -105,7 +105,7 @@ struct LaunchConfig {
     Form form;
     int cpt_tmpl;      // register-held chunks per wave: 0 (re-read), 2 or 4
     int vpt_tmpl;      // register-held variables per thread (resident form): 4 or 8
-    int dclass;        // 0: degrees exactly 6; 1: degrees 2..8
+    int dclass;        // 0: degrees exactly 6; 1: degrees 2..8; 2: degrees 6..8 (resident form)
     int dv;            // every variable has this degree (0: mixed), resident form
     int slot_mode;     // 0 global float slots, 1 LDS float slots, 2 LDS fixed-point accumulators
     bool half;         // fp16 state storage (streamed only)

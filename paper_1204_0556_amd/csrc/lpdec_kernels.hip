@@ -252,6 +252,14 @@ __device__ __forceinline__ void lds_copy4(const float *src, float *lds_base) {
     __builtin_amdgcn_global_load_lds(src, lds_base, 4, 0, 0);
 }
 
+// A pointer read from a kernel argument structure is generic to the compiler,
+// and a generic load waits on LDS traffic as well; this one is known to point to
+// global memory.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *as_global(const T *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+
 template <int DMIN, int DMAX, typename F>
 __device__ __forceinline__ void dispatch_degree(int d, F &&f) {
     if constexpr (DMIN == DMAX) {
@@ -304,14 +312,15 @@ __device__ __forceinline__ float from_fixed(unsigned long long a) {
 }
 
 // one check update of degree D on registers z,u (length DMAX arrays); x is read
-// from xs with stride XS (2 when x shares an accumulator entry)
-template <int D, int XS = 1>
-__device__ __forceinline__ void check_update(float *z, float *u, const uint32_t *meta, const float *xs,
+// from xs with stride XS (2 when x shares an accumulator entry); edge k's
+// metadata is meta[MS * k] (registers: MS = 1; the lane-minor array: MS = 64)
+template <int D, int XS = 1, int MS = 1, typename MP = const uint32_t *>
+__device__ __forceinline__ void check_update(float *z, float *u, MP meta, const float *xs,
                                              float rho, float &rp, float &rd) {
     float v[D], zn[D], xv[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        xv[k] = xs[XS * (meta[k] & 0xffffu)];
+        xv[k] = xs[XS * (meta[MS * k] & 0xffffu)];
         v[k] = fmaf(rho, xv[k] - z[k], z[k]) + u[k];  // q + u with q = rho x + (1-rho) z
     }
     project_pp<D>(v, zn);
@@ -391,10 +400,15 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
 
     constexpr int NC = CPT > 0 ? CPT : 1;
     float z[NC][DMAX], u[NC][DMAX];
+    // Packed edge metadata of the register-held chunks: kept in registers for
+    // degree-6 codes; for checks of degree up to 8 the register budget of 1024
+    // threads only holds z and u, and the metadata (per code, shared by every
+    // frame, so L2-resident) is re-read where it is used.
+    constexpr bool MREG = DMAX <= 6;
     constexpr int GQ = STG ? 4 : 1;  // STG: gamma/mu of this thread's variables tid + t NT
     float gq[GQ];
     constexpr bool LBAR = SM != 0;  // phase barriers need only order LDS
-    uint32_t meta[NC][DMAX];
+    uint32_t meta[NC][MREG ? DMAX : 1];
     int cdeg[NC], coff[NC];
     bool cval[NC];
     float vg[VPT > 0 ? VPT : 1];
@@ -491,9 +505,11 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                     cdeg[k] = has ? __builtin_amdgcn_readfirstlane(C.chunk_deg[c]) : 0;
                     coff[k] = has ? __builtin_amdgcn_readfirstlane(C.chunk_off[c]) : 0;
                     cval[k] = has && (lane < C.chunk_cnt[c]);
+                    if constexpr (MREG) {
 #pragma unroll
-                    for (int e = 0; e < DMAX; ++e)
-                        meta[k][e] = (cval[k] && e < cdeg[k]) ? C.edge_meta[coff[k] + e * kWave + lane] : 0u;
+                        for (int e = 0; e < DMAX; ++e)
+                            meta[k][e] = (cval[k] && e < cdeg[k]) ? C.edge_meta[coff[k] + e * kWave + lane] : 0u;
+                    }
                 }
                 if constexpr (VPT > 0 && DV == 0) {
 #pragma unroll
@@ -625,9 +641,14 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                         }
                     }
                     if (cval[k]) {  // one lane mask per chunk; all-degree-6 codes need no per-edge test
+                        const auto mp = as_global(C.edge_meta) + coff[k] + lane;
 #pragma unroll
-                        for (int e = 0; e < DMAX; ++e)
-                            if (DMIN == DMAX || e < cdeg[k]) slots[meta[k][e] >> 16] = z[k][e] - u[k][e];
+                        for (int e = 0; e < DMAX; ++e) {
+                            if (DMIN == DMAX || e < cdeg[k]) {
+                                const uint32_t mt = MREG ? meta[k][MREG ? e : 0] : mp[e * kWave];
+                                slots[mt >> 16] = z[k][e] - u[k][e];
+                            }
+                        }
                     }
                 }
             } else {
@@ -678,7 +699,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             } else {
                 // gamma/mu: straight from the frame's LLRs when variables keep their
                 // order, else from the copy staged in internal order
-                const float *gsrc = C.var_identity ? gam : gmu_row;
+                const auto gsrc = as_global(C.var_identity ? gam : gmu_row);
                 const float gscale = C.var_identity ? ip.mu_inv : 1.0f;
                 if constexpr (STG) {  // gamma/mu taken from the staging area in phase A
 #pragma unroll
@@ -710,11 +731,26 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                             }
                         }
                     }
-                } else {
-                    for (int i = tid; i < C.n; i += NT) {
-                        const int2 vi = C.var_info[i];
-                        xs[i] = x_update(slots, VarLoc{vi.x & 0xffffff, vi.x >> 24, __int_as_float(vi.y)},
-                                         gsrc[i] * gscale);
+                } else {  // mixed degrees: four variables per pass, loads first
+                    // var_info entries {slot0 | deg << 24, 1/deg} as one 8-byte word
+                    const auto vinfo = as_global(reinterpret_cast<const unsigned long long *>(C.var_info));
+                    for (int i0 = tid; i0 < C.n; i0 += 4 * NT) {
+                        unsigned long long vi[4];
+                        float g[4];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int i = i0 + t * NT;
+                            vi[t] = (i < C.n) ? vinfo[i] : 0ull;
+                            g[t] = (i < C.n) ? gsrc[i] : 0.0f;
+                        }
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int i = i0 + t * NT;
+                            const int lo = (int)(unsigned)vi[t], hi = (int)(unsigned)(vi[t] >> 32);
+                            if (i < C.n)
+                                xs[i] = x_update(slots, VarLoc{lo & 0xffffff, lo >> 24, __int_as_float(hi)},
+                                                 g[t] * gscale);
+                        }
                     }
                 }
             }
@@ -726,10 +762,18 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 for (int k = 0; k < CPT; ++k) {
                     if (cdeg[k] == 0) continue;  // wave-uniform
                     if (cval[k]) {
-                        dispatch_degree<DMIN, DMAX>(cdeg[k], [&](auto dc) {
-                            constexpr int D = decltype(dc)::value;
-                            check_update<D, XS>(z[k], u[k], meta[k], xs, ip.rho, rp, rd);
-                        });
+                        if constexpr (MREG) {
+                            dispatch_degree<DMIN, DMAX>(cdeg[k], [&](auto dc) {
+                                constexpr int D = decltype(dc)::value;
+                                check_update<D, XS>(z[k], u[k], meta[k], xs, ip.rho, rp, rd);
+                            });
+                        } else {  // metadata read from memory
+                            dispatch_degree<DMIN, DMAX>(cdeg[k], [&](auto dc) {
+                                constexpr int D = decltype(dc)::value;
+                                check_update<D, XS, kWave>(z[k], u[k], as_global(C.edge_meta) + coff[k] + lane, xs,
+                                                           ip.rho, rp, rd);
+                            });
+                        }
                     }
                     if constexpr (!RES) {
 #pragma unroll
@@ -1021,31 +1065,49 @@ static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const 
                 if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4) LPD_GO(2, 4, true, true, 1, false, 768);
                 if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8) LPD_GO(2, 8, true, true, 1, false, 768);
             }
+            // checks of degree 6..8: z, u of up to eight chunks per wave in registers,
+            // variables read from the code's tables (VPT 0); the more chunks per
+            // wave, the fewer waves (the register file holds the frame either way)
+            if constexpr (DMIN == 6 && DMAX == 8) {
+                if (cfg.cpt_tmpl == 1) LPD_GO(1, 0, true, true, 1, false);
+                if (cfg.cpt_tmpl == 2) LPD_GO(2, 0, true, true, 1, false);
+                if (cfg.cpt_tmpl == 4) LPD_GO(4, 0, true, true, 1, false, 768);
+                if (cfg.cpt_tmpl == 8) LPD_GO(8, 0, true, true, 1, false, 512);
+            }
             break;
-        case Form::PersistentGlobal:
-            if (cfg.slot_mode == 1) LPD_GO(0, 0, false, true, 1, false);
-            if (cfg.slot_mode == 2) LPD_GO(0, 0, false, true, 2, false);
-            LPD_GO(0, 0, false, true, 0, false);
-        case Form::Streamed:
-            if (cfg.slot_mode == 1) {
-                // register-held chunks: degree-6 codes only (DMAX = 8 register arrays spill)
-                if constexpr (DMIN == 6 && DMAX == 6) {
-                    if (cfg.staged && cfg.cpt_tmpl == 2 && cfg.threads <= 768 && !cfg.half)
-                        LPD_GO(2, 0, false, false, 1, false, 768, 0, true);
-                    if (cfg.cpt_tmpl == 2 && cfg.threads <= 768 && !cfg.half) LPD_GO(2, 0, false, false, 1, false, 768);
-                    if (cfg.cpt_tmpl == 2 && cfg.threads <= 768 && cfg.half) LPD_GO(2, 0, false, false, 1, true, 768);
-                    if (cfg.cpt_tmpl == 2 && !cfg.half) LPD_GO(2, 0, false, false, 1, false);
-                    if (cfg.cpt_tmpl == 2 && cfg.half) LPD_GO(2, 0, false, false, 1, true);
+        default:
+            // degrees 6..8 are built for the resident form only
+            if constexpr (!(DMIN == 6 && DMAX == 8)) {
+                switch (cfg.form) {
+                    case Form::PersistentGlobal:
+                        if (cfg.slot_mode == 1) LPD_GO(0, 0, false, true, 1, false);
+                        if (cfg.slot_mode == 2) LPD_GO(0, 0, false, true, 2, false);
+                        LPD_GO(0, 0, false, true, 0, false);
+                    case Form::Streamed:
+                        if (cfg.slot_mode == 1) {
+                            // register-held chunks: degree-6 codes only (DMAX = 8 register arrays spill)
+                            if constexpr (DMIN == 6 && DMAX == 6) {
+                                if (cfg.staged && cfg.cpt_tmpl == 2 && cfg.threads <= 768 && !cfg.half)
+                                    LPD_GO(2, 0, false, false, 1, false, 768, 0, true);
+                                if (cfg.cpt_tmpl == 2 && cfg.threads <= 768 && !cfg.half) LPD_GO(2, 0, false, false, 1, false, 768);
+                                if (cfg.cpt_tmpl == 2 && cfg.threads <= 768 && cfg.half) LPD_GO(2, 0, false, false, 1, true, 768);
+                                if (cfg.cpt_tmpl == 2 && !cfg.half) LPD_GO(2, 0, false, false, 1, false);
+                                if (cfg.cpt_tmpl == 2 && cfg.half) LPD_GO(2, 0, false, false, 1, true);
+                            }
+                            if (!cfg.half) LPD_GO(0, 0, false, false, 1, false);
+                            LPD_GO(0, 0, false, false, 1, true);
+                        }
+                        if (cfg.slot_mode == 2) {
+                            if (!cfg.half) LPD_GO(0, 0, false, false, 2, false);
+                            LPD_GO(0, 0, false, false, 2, true);
+                        }
+                        if (!cfg.half) LPD_GO(0, 0, false, false, 0, false);
+                        LPD_GO(0, 0, false, false, 0, true);
+                    default:
+                        break;
                 }
-                if (!cfg.half) LPD_GO(0, 0, false, false, 1, false);
-                LPD_GO(0, 0, false, false, 1, true);
             }
-            if (cfg.slot_mode == 2) {
-                if (!cfg.half) LPD_GO(0, 0, false, false, 2, false);
-                LPD_GO(0, 0, false, false, 2, true);
-            }
-            if (!cfg.half) LPD_GO(0, 0, false, false, 0, false);
-            LPD_GO(0, 0, false, false, 0, true);
+            break;
     }
 #undef LPD_GO
     return hipErrorInvalidValue;
@@ -1054,6 +1116,7 @@ static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const 
 hipError_t launch_decode(const LaunchConfig &cfg, const DevCode *codes_dev, const FrameBatch &fb,
                          const IterParams &ip, const StateIO &sio, const StreamArgs &sa, hipStream_t stream) {
     if (cfg.dclass == 0) return go_range<6, 6>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
+    if (cfg.dclass == 2) return go_range<6, 8>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
     return go_range<2, 8>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
 }
 
@@ -1064,6 +1127,7 @@ hipError_t decode_query(const LaunchConfig &cfg, KernelQuery *q) {
     StreamArgs sa{};
     *q = KernelQuery{};
     if (cfg.dclass == 0) return go_range<6, 6>(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
+    if (cfg.dclass == 2) return go_range<6, 8>(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
     return go_range<2, 8>(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
 }
 

@@ -1,0 +1,86 @@
+"""GPU: the irregular rate-1/2 codes (variable degrees {2,3,6}, check degrees 6..8) in
+the register-resident form, which holds up to eight degree-8 chunks per wave and
+reads the edge metadata and variable tables from memory.
+
+Messages after a fixed number of iterations are compared with the oracle, and the
+resident, persistent-global and streamed forms with each other bitwise (every form
+of a code uses the same chunk-to-wave plan, so the arithmetic is the same).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+lp = None
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    global lp
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    import paper_1204_0556_amd as m
+    lp = m
+    yield
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("n", W.IRREGULAR_LENGTHS)
+def test_resident_messages_after_k_iterations(n):
+    H = W.irregular_half(n)
+    code = lp.Code(H)
+    assert code.info["resident_capable"]
+    assert code.launch_info(mode=lp.MODE_RESIDENT)["mode"] == lp.MODE_RESIDENT
+    frames = 6 if n > 4000 else 12
+    llr = W.awgn_batch(H, frames, 2.0, tag="irr-fixedk")
+    for K in (1, 25):
+        print(f"irregular n={n} K={K} frames={frames}", flush=True)
+        x, it, fl, z, u = lp.decode_state(code, dev(llr), mode=lp.MODE_RESIDENT, tol=0.0, max_iter=K)
+        ref = oracle.decode(H, llr, max_iter=K, tol=0.0, state=True)
+        assert np.all(host(it) == K)
+        assert np.abs(host(x) - ref.x).max() < 1e-4
+        assert np.abs(host(z) - ref.z).max() < 1e-4
+        assert np.abs(host(u) - ref.u).max() < 1e-4
+
+
+@pytest.mark.parametrize("n", [576, 4608, 8064])
+def test_forms_agree_bitwise_irregular(n):
+    H = W.irregular_half(n)
+    code = lp.Code(H)
+    llr = W.awgn_batch(H, 24, 1.75, tag="irr-forms")
+    llr[5, 7] = np.nan  # one invalid frame among them
+    outs = []
+    for m in (lp.MODE_RESIDENT, lp.MODE_PERSISTENT_GLOBAL, lp.MODE_STREAMED):
+        print(f"irregular forms n={n} mode={m}", flush=True)
+        x, it, fl = lp.decode(code, dev(llr), mode=m, max_iter=150)
+        outs.append((host(x), host(it), host(fl)))
+    assert outs[0][2][5] == lp.FLAG_INVALID and outs[0][1][5] == 0
+    for o in outs[1:]:
+        assert np.array_equal(o[1], outs[0][1])
+        assert np.array_equal(o[2], outs[0][2])
+        assert np.abs(o[0] - outs[0][0]).max() == 0.0
+
+
+def test_resident_whole_decodes_against_oracle():
+    H = W.irregular_half(2304)
+    llr = np.concatenate([W.awgn_batch(H, 16, s, tag="irr-whole") for s in (1.5, 2.5)])
+    print(f"irregular whole decodes frames={len(llr)}", flush=True)
+    x, it, fl = lp.decode(lp.Code(H), dev(llr), mode=lp.MODE_RESIDENT)
+    x, it, fl = host(x), host(it), host(fl)
+    ref = oracle.decode(H, llr)
+    ambiguous = np.any(np.abs(ref.x - 0.5) < 1e-3, axis=1)
+    same = np.all((x >= 0.5) == (ref.x >= 0.5), axis=1)
+    assert np.all(same | ambiguous)
+    assert np.mean(np.abs(it.astype(int) - ref.iters) <= 2) >= 0.95
