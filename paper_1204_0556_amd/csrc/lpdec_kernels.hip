@@ -260,6 +260,25 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T *as_global(
     return (const __attribute__((address_space(1))) T *)p;
 }
 
+// The same pointer, hidden from the optimiser (loads through it are not moved
+// out of the loop they are written in).
+template <typename T>
+__device__ __forceinline__ const T *opaque_ptr(const T *p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// Packed metadata of one chunk of degree d (0: no chunk) into m[0..D): loads for
+// every e, the index clamped to the chunk's last row, so they can be issued
+// without branches ahead of their use (rows e >= d repeat row d-1 and are unused).
+template <int D>
+__device__ __forceinline__ void load_meta(uint32_t *m, const uint32_t *edge_meta, int off, int d, int lane) {
+    const auto mp = as_global(edge_meta) + off + lane;
+    const int last = max(d, 1) - 1;
+#pragma unroll
+    for (int e = 0; e < D; ++e) m[e] = mp[min(e, last) * kWave];
+}
+
 template <int DMIN, int DMAX, typename F>
 __device__ __forceinline__ void dispatch_degree(int d, F &&f) {
     if constexpr (DMIN == DMAX) {
@@ -312,15 +331,14 @@ __device__ __forceinline__ float from_fixed(unsigned long long a) {
 }
 
 // one check update of degree D on registers z,u (length DMAX arrays); x is read
-// from xs with stride XS (2 when x shares an accumulator entry); edge k's
-// metadata is meta[MS * k] (registers: MS = 1; the lane-minor array: MS = 64)
-template <int D, int XS = 1, int MS = 1, typename MP = const uint32_t *>
-__device__ __forceinline__ void check_update(float *z, float *u, MP meta, const float *xs,
+// from xs with stride XS (2 when x shares an accumulator entry)
+template <int D, int XS = 1>
+__device__ __forceinline__ void check_update(float *z, float *u, const uint32_t *meta, const float *xs,
                                              float rho, float &rp, float &rd) {
     float v[D], zn[D], xv[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        xv[k] = xs[XS * (meta[MS * k] & 0xffffu)];
+        xv[k] = xs[XS * (meta[k] & 0xffffu)];
         v[k] = fmaf(rho, xv[k] - z[k], z[k]) + u[k];  // q + u with q = rho x + (1-rho) z
     }
     project_pp<D>(v, zn);
@@ -405,6 +423,12 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
     // threads only holds z and u, and the metadata (per code, shared by every
     // frame, so L2-resident) is re-read where it is used.
     constexpr bool MREG = DMAX <= 6;
+    // register-resident form: phase C writes each chunk's slots for the next
+    // iteration right after updating it (phase A fused into phase C; phase C
+    // reads only x, never the slots).  With metadata from memory this halves its
+    // loads; with two chunks per wave it measured 3 % faster, with one chunk per
+    // wave slower, so that variant keeps the separate pass.
+    constexpr bool FUSED_A = RES && (!MREG || CPT >= 2);
     constexpr int GQ = STG ? 4 : 1;  // STG: gamma/mu of this thread's variables tid + t NT
     float gq[GQ];
     constexpr bool LBAR = SM != 0;  // phase barriers need only order LDS
@@ -640,14 +664,19 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                             }
                         }
                     }
-                    if (cval[k]) {  // one lane mask per chunk; all-degree-6 codes need no per-edge test
-                        const auto mp = as_global(C.edge_meta) + coff[k] + lane;
+                    if constexpr (MREG) {
+                        if (cval[k]) {  // one lane mask per chunk; all-degree-6 codes need no per-edge test
 #pragma unroll
-                        for (int e = 0; e < DMAX; ++e) {
-                            if (DMIN == DMAX || e < cdeg[k]) {
-                                const uint32_t mt = MREG ? meta[k][MREG ? e : 0] : mp[e * kWave];
-                                slots[mt >> 16] = z[k][e] - u[k][e];
-                            }
+                            for (int e = 0; e < DMAX; ++e)
+                                if (DMIN == DMAX || e < cdeg[k]) slots[meta[k][e] >> 16] = z[k][e] - u[k][e];
+                        }
+                    } else {
+                        uint32_t mt[DMAX];
+                        load_meta<DMAX>(mt, opaque_ptr(C.edge_meta), coff[k], cdeg[k], lane);
+                        if (cval[k]) {
+#pragma unroll
+                            for (int e = 0; e < DMAX; ++e)
+                                if (e < cdeg[k]) slots[mt[e] >> 16] = z[k][e] - u[k][e];
                         }
                     }
                 }
@@ -757,23 +786,43 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         };
 
         auto phase_c = [&](float &rp, float &rd) {
-            if constexpr (CPT > 0) {
+            if constexpr (CPT > 0 && !MREG) {
+                // metadata read from memory, one chunk ahead of its use; each chunk's
+                // slot writes for the next iteration follow its update, reusing it
+                // (the table pointer is made opaque so that the loads stay in the
+                // iteration instead of being hoisted out of it into registers)
+                const uint32_t *em = opaque_ptr(C.edge_meta);
+                uint32_t mcur[DMAX], mnext[DMAX];
+                load_meta<DMAX>(mcur, em, coff[0], cdeg[0], lane);
+#pragma unroll
+                for (int k = 0; k < CPT; ++k) {
+                    if (k + 1 < CPT) load_meta<DMAX>(mnext, em, coff[k + 1], cdeg[k + 1], lane);
+                    if (cdeg[k] != 0 && cval[k]) {  // cdeg wave-uniform
+                        dispatch_degree<DMIN, DMAX>(cdeg[k], [&](auto dc) {
+                            constexpr int D = decltype(dc)::value;
+                            check_update<D, XS>(z[k], u[k], mcur, xs, ip.rho, rp, rd);
+                            if constexpr (FUSED_A) {
+#pragma unroll
+                                for (int e = 0; e < D; ++e) slots[mcur[e] >> 16] = z[k][e] - u[k][e];
+                            }
+                        });
+                    }
+#pragma unroll
+                    for (int e = 0; e < DMAX; ++e) mcur[e] = mnext[e];
+                }
+            } else if constexpr (CPT > 0) {
 #pragma unroll
                 for (int k = 0; k < CPT; ++k) {
                     if (cdeg[k] == 0) continue;  // wave-uniform
                     if (cval[k]) {
-                        if constexpr (MREG) {
-                            dispatch_degree<DMIN, DMAX>(cdeg[k], [&](auto dc) {
-                                constexpr int D = decltype(dc)::value;
-                                check_update<D, XS>(z[k], u[k], meta[k], xs, ip.rho, rp, rd);
-                            });
-                        } else {  // metadata read from memory
-                            dispatch_degree<DMIN, DMAX>(cdeg[k], [&](auto dc) {
-                                constexpr int D = decltype(dc)::value;
-                                check_update<D, XS, kWave>(z[k], u[k], as_global(C.edge_meta) + coff[k] + lane, xs,
-                                                           ip.rho, rp, rd);
-                            });
-                        }
+                        dispatch_degree<DMIN, DMAX>(cdeg[k], [&](auto dc) {
+                            constexpr int D = decltype(dc)::value;
+                            check_update<D, XS>(z[k], u[k], meta[k], xs, ip.rho, rp, rd);
+                            if constexpr (FUSED_A) {
+#pragma unroll
+                                for (int e = 0; e < D; ++e) slots[meta[k][e] >> 16] = z[k][e] - u[k][e];
+                            }
+                        });
                     }
                     if constexpr (!RES) {
 #pragma unroll
@@ -847,7 +896,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 // accumulator mode: the next phase A adds into the entries that
                 // phase C is still reading x from
                 if constexpr (SM == 2) wg_barrier<LBAR>();
-                phase_a();
+                if constexpr (!FUSED_A) phase_a();  // else done chunk by chunk in phase C
                 wg_barrier<LBAR>();
                 if (__builtin_amdgcn_readfirstlane(converged(it & 1))) { conv = true; break; }
                 if (it >= ip.max_iter) break;
