@@ -429,6 +429,9 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
     // loads; with two chunks per wave it measured 3 % faster, with one chunk per
     // wave slower, so that variant keeps the separate pass.
     constexpr bool FUSED_A = RES && (!MREG || CPT >= 2);
+    // variables per pass of the mixed-degree variable phase (their table entries
+    // and gamma/mu are loaded together before the sums)
+    constexpr int VB = 4;
     constexpr int GQ = STG ? 4 : 1;  // STG: gamma/mu of this thread's variables tid + t NT
     float gq[GQ];
     constexpr bool LBAR = SM != 0;  // phase barriers need only order LDS
@@ -760,20 +763,20 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                             }
                         }
                     }
-                } else {  // mixed degrees: four variables per pass, loads first
+                } else {  // mixed degrees: VB variables per pass, loads first
                     // var_info entries {slot0 | deg << 24, 1/deg} as one 8-byte word
                     const auto vinfo = as_global(reinterpret_cast<const unsigned long long *>(C.var_info));
-                    for (int i0 = tid; i0 < C.n; i0 += 4 * NT) {
-                        unsigned long long vi[4];
-                        float g[4];
+                    for (int i0 = tid; i0 < C.n; i0 += VB * NT) {
+                        unsigned long long vi[VB];
+                        float g[VB];
 #pragma unroll
-                        for (int t = 0; t < 4; ++t) {
+                        for (int t = 0; t < VB; ++t) {
                             const int i = i0 + t * NT;
                             vi[t] = (i < C.n) ? vinfo[i] : 0ull;
                             g[t] = (i < C.n) ? gsrc[i] : 0.0f;
                         }
 #pragma unroll
-                        for (int t = 0; t < 4; ++t) {
+                        for (int t = 0; t < VB; ++t) {
                             const int i = i0 + t * NT;
                             const int lo = (int)(unsigned)vi[t], hi = (int)(unsigned)(vi[t] >> 32);
                             if (i < C.n)
