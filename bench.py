@@ -437,7 +437,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", default="auto", choices=["auto", "resident", "persistent_global", "streamed"])
-    ap.add_argument("--cpu-frames", type=int, default=4096, help="oracle sample size (frames)")
+    ap.add_argument("--cpu-frames", type=int, default=6144,
+                    help="oracle sample size (frames; about 10-15 s of host time)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the plain and streamed comparisons")
     ap.add_argument("--workload", default="headline",
