@@ -254,6 +254,26 @@ def workload_precision(args, lp, W, torch):
     }
 
 
+def measured_copy_gbs(torch, nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Achievable HBM bandwidth: a plain device-to-device copy of nbytes (read +
+    write counted), timed with HIP events on the current stream."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * nbytes / (ms / 1e3) / 1e9
+
+
 def _timed(torch, fn, steps=1, warmup=1):
     """Run fn warmup + steps times; return (last result, mean ms of the timed runs)
     from HIP events on the current stream."""
@@ -600,12 +620,14 @@ def main():
         sit = out[1].cpu().numpy().astype(np.int64)
         sfi = int(sit.sum())
         sach = B * sfi / (sms / 1e3) / 1e9
+        copy_gbs = measured_copy_gbs(torch)
         res["streamed"] = {"mbit_s": round(F * H.n / (sms / 1e3) / 1e6, 2), "ms": round(sms, 3),
                            "algorithmic_bytes": B * sfi,
                            "traffic_bytes": profiled_traffic("k_decode_streamed_n2640_headline",
                                                              "traffic_bytes_per_decode"),
                            "launches": int(sit.max()), "hbm_achieved_gbs": round(sach, 1),
-                           "hbm_frac": round(sach / HBM_PEAK_GBS, 4), "bytes_per_frame_iter": B}
+                           "hbm_frac": round(sach / HBM_PEAK_GBS, 4), "bytes_per_frame_iter": B,
+                           "copy_ceiling_gbs": round(copy_gbs, 1), "frac_of_copy": round(sach / copy_gbs, 4)}
         # plain: one frame per launch sequence (streamed form, batch of one), sampled
         sample = np.concatenate([b * FRAMES_PER_SNR + np.arange(8) for b in range(len(W.HEADLINE_SNRS))])
         one = [(torch.empty((1, H.n), dtype=torch.float32, device=dev),

@@ -84,3 +84,25 @@ def test_resident_whole_decodes_against_oracle():
     same = np.all((x >= 0.5) == (ref.x >= 0.5), axis=1)
     assert np.all(same | ambiguous)
     assert np.mean(np.abs(it.astype(int) - ref.iters) <= 2) >= 0.95
+
+
+def test_degree6_code_in_a_degree_6_to_8_launch():
+    """A (3,6) code batched with irregular codes runs in the degree-6..8 resident kernel
+    (metadata from memory, mixed-degree variable tables); its frames still equal
+    the degree-6 kernel's single-code decodes bitwise."""
+    codes_h = [W.gallager36(2640), W.irregular_half(576), W.gallager36(96), W.irregular_half(2304)]
+    handles = [lp.Code(H) for H in codes_h]
+    batch = W.mixed_batch(codes_h, 160, 1.5, 3.0, tag="mix6-8", seed=3)
+    flat, off = batch.flat_llr()
+    print(f"mixed degree-6 / irregular batch frames={batch.frames}", flush=True)
+    x, it, fl = lp.decode_multi(handles, batch.code_of_frame, off, dev(flat), off, flat.size, max_iter=300)
+    x, it, fl = host(x), host(it), host(fl)
+    for c, H in enumerate(codes_h):
+        idx = np.nonzero(batch.code_of_frame == c)[0]
+        if idx.size == 0:
+            continue
+        llr = np.stack([batch.llr[f] for f in idx])
+        xs, its, fls = (host(t) for t in lp.decode(handles[c], dev(llr), max_iter=300))
+        for k, f in enumerate(idx):
+            assert np.array_equal(x[off[f]:off[f] + H.n], xs[k])
+            assert it[f] == its[k] and fl[f] == fls[k]
