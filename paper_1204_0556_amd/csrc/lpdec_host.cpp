@@ -501,7 +501,12 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
         // previous call on this workspace may still be copying from it, so wait
         // for that call first (the source must outlive the asynchronous copy).
         const size_t tbl_bytes = ((sizeof(DevCode) * ncodes + 255) / 256) * 256;
-        const size_t bytes = tbl_bytes + (size_t)nframes * (2 * sizeof(int64_t) + sizeof(int32_t));
+        // frames of several codes are handed out largest code first, so that the
+        // launch ends on short frames (less idle time in its tail)
+        const bool ordered = ncodes > 1 && code_of_frame &&
+                             (cfg.form == Form::Resident || cfg.form == Form::PersistentGlobal);
+        const size_t bytes = tbl_bytes + (size_t)nframes * (2 * sizeof(int64_t) + sizeof(int32_t)) +
+                             (ordered ? (size_t)nframes * sizeof(int32_t) : 0);
         if (ws.last) HIP_TRY(hipEventSynchronize(ws.last));
         if (ws.host_meta_bytes < bytes) {
             if (ws.host_meta) HIP_TRY(hipHostFree(ws.host_meta));
@@ -521,12 +526,20 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
             h_xoff[f] = x_off ? x_off[f] : (int64_t)f * codes[0]->dc.n;
             h_cof[f] = code_of_frame ? code_of_frame[f] : 0;
         }
+        if (ordered) {
+            int32_t *h_ord = h_cof + nframes;
+            for (int f = 0; f < nframes; ++f) h_ord[f] = f;
+            std::stable_sort(h_ord, h_ord + nframes, [&](int a, int b) {
+                return codes[code_of_frame[a]]->dc.E > codes[code_of_frame[b]]->dc.E;
+            });
+        }
         HIP_TRY(hipMemcpyAsync(ws.frame_meta.p, h, bytes, hipMemcpyHostToDevice, stream));
         char *d = static_cast<char *>(ws.frame_meta.p);
         codes_dev = reinterpret_cast<const DevCode *>(d);
         fb.llr_off = reinterpret_cast<const int64_t *>(d + tbl_bytes);
         fb.x_off = fb.llr_off + nframes;
         if (code_of_frame) fb.code_of_frame = reinterpret_cast<const int32_t *>(fb.x_off + nframes);
+        if (ordered) fb.order = fb.code_of_frame + nframes;
     }
     // invalid-input flags for every frame, read by the decode kernels
     {

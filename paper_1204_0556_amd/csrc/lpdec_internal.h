@@ -64,6 +64,7 @@ struct FrameBatch {
     uint8_t *flags_out;
     int *queue;                 // device work counter (persistent kernels)
     int *done;                  // optional [nframes] completion flags (host-visible), set last
+    const int *order;           // device [nframes] or nullptr: queue position -> frame (persistent forms)
 };
 
 struct IterParams {

@@ -493,7 +493,10 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             // the frame index and the workgroup votes below are moved to scalar
             // registers: branches on them are then uniform, so the frame loop
             // keeps one shape for all lanes (lane 0 fetches the next frame)
-            if (tid == 0) s_frame = atomicAdd(fb.queue, 1);
+            if (tid == 0) {
+                const int q = atomicAdd(fb.queue, 1);
+                s_frame = (fb.order && q < fb.nframes) ? fb.order[q] : q;
+            }
             __syncthreads();
             f = __builtin_amdgcn_readfirstlane(s_frame);
             __syncthreads();
