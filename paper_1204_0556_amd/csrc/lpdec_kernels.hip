@@ -419,9 +419,9 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
     constexpr int NC = CPT > 0 ? CPT : 1;
     float z[NC][DMAX], u[NC][DMAX];
     // Packed edge metadata of the register-held chunks: kept in registers for
-    // degree-6 codes; for checks of degree up to 8 the register budget of 1024
-    // threads only holds z and u, and the metadata (per code, shared by every
-    // frame, so L2-resident) is re-read where it is used.
+    // degree-6 codes; with checks of degree up to 8 the registers hold only z and
+    // u (up to eight chunks per wave), and the metadata (per code, shared by every
+    // frame, so L2-resident) is loaded again each iteration, one chunk ahead.
     constexpr bool MREG = DMAX <= 6;
     // register-resident form: phase C writes each chunk's slots for the next
     // iteration right after updating it (phase A fused into phase C; phase C
