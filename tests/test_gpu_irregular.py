@@ -106,3 +106,35 @@ def test_degree6_code_in_a_degree_6_to_8_launch():
         for k, f in enumerate(idx):
             assert np.array_equal(x[off[f]:off[f] + H.n], xs[k])
             assert it[f] == its[k] and fl[f] == fls[k]
+
+
+def test_resident_warm_start_resume_is_exact():
+    H = W.irregular_half(4608)
+    code = lp.Code(H)
+    llr = W.awgn_batch(H, 6, 1.5, tag="irr-warm")
+    print(f"irregular warm start n={H.n}", flush=True)
+    a = lp.decode_state(code, dev(llr), tol=0.0, max_iter=30, mode=lp.MODE_RESIDENT)
+    b = lp.decode_state(code, dev(llr), tol=0.0, max_iter=12, mode=lp.MODE_RESIDENT)
+    c = lp.decode_state(code, dev(llr), z=b[3], u=b[4], state_in=True, tol=0.0, max_iter=18,
+                        mode=lp.MODE_RESIDENT)
+    assert np.array_equal(host(a[3]), host(c[3])) and np.array_equal(host(a[4]), host(c[4]))
+    assert np.array_equal(host(a[0]), host(c[0]))
+
+
+def test_resident_tuning_and_autotune_keep_results():
+    H = W.irregular_half(1152)
+    code = lp.Code(H)
+    llr = torch.from_numpy(np.concatenate([W.awgn_batch(H, 128, s, tag="irr-tune") for s in (1.5, 2.5)])).cuda()
+    kw = dict(W.PAPER_PARAMS, max_iter=300, mode=lp.MODE_RESIDENT)
+    ref = [host(t) for t in lp.decode(code, llr, **kw)]
+    for bpc in (1, 2, 3):
+        code.set_tuning(lp.MODE_RESIDENT, bpc, -1)
+        assert code.launch_info(mode=lp.MODE_RESIDENT)["blocks_per_cu"] == bpc
+        got = [host(t) for t in lp.decode(code, llr, **kw)]
+        for r, g in zip(ref, got):
+            assert np.array_equal(r, g), bpc
+    (bpc, _), times = code.autotune(llr, max_blocks_per_cu=3, **kw)
+    assert 1 <= bpc <= 3 and times
+    got = [host(t) for t in lp.decode(code, llr, **kw)]
+    for r, g in zip(ref, got):
+        assert np.array_equal(r, g)
