@@ -501,9 +501,12 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
         // previous call on this workspace may still be copying from it, so wait
         // for that call first (the source must outlive the asynchronous copy).
         const size_t tbl_bytes = ((sizeof(DevCode) * ncodes + 255) / 256) * 256;
-        // frames of several codes are handed out largest code first, so that the
-        // launch ends on short frames (less idle time in its tail)
-        const bool ordered = ncodes > 1 && code_of_frame &&
+        // frames of codes of different sizes are handed out largest code first, so
+        // that the launch ends on short frames (less idle time in its tail); the
+        // lookup costs a dependent load per frame, so equal-size codes skip it
+        bool mixed_sizes = false;
+        for (int c = 1; c < ncodes; ++c) mixed_sizes = mixed_sizes || codes[c]->dc.E != codes[0]->dc.E;
+        const bool ordered = mixed_sizes && code_of_frame &&
                              (cfg.form == Form::Resident || cfg.form == Form::PersistentGlobal);
         const size_t bytes = tbl_bytes + (size_t)nframes * (2 * sizeof(int64_t) + sizeof(int32_t)) +
                              (ordered ? (size_t)nframes * sizeof(int32_t) : 0);
