@@ -254,6 +254,16 @@ def workload_precision(args, lp, W, torch):
     }
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def measured_copy_gbs(torch, nbytes: int = 1 << 30, reps: int = 5) -> float:
     """Achievable HBM bandwidth: a plain device-to-device copy of nbytes (read +
     write counted), timed with HIP events on the current stream."""
@@ -673,10 +683,19 @@ def main():
         t0 = time.perf_counter()
         ref = oracle.decode(H, llr_h[sample], nthreads=cores, **P)
         ct = time.perf_counter() - t0
+        # one thread on a smaller sample (the first frames of each Eb/N0 block, ~4 s)
+        per1 = max(1, per // 96)
+        sample1 = np.concatenate([b * FRAMES_PER_SNR + np.arange(per1) for b in range(len(W.HEADLINE_SNRS))])
+        t0 = time.perf_counter()
+        oracle.decode(H, llr_h[sample1], nthreads=1, **P)
+        ct1 = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": round(len(sample) * H.n / ct / 1e6, 3), "unit": "Mbit/s", "cores": cores,
                                "kind": "oracle",
                                "sample": f"{len(sample)} frames ({per} per Eb/N0, same LLRs), FP64 C oracle, "
-                                         f"{ct:.1f} s, mean iterations {ref.iters.mean():.1f}"}
+                                         f"{ct:.1f} s, mean iterations {ref.iters.mean():.1f}",
+                               "single_thread": {"value": round(len(sample1) * H.n / ct1 / 1e6, 4),
+                                                 "frames": int(len(sample1)), "seconds": round(ct1, 2)},
+                               "cpu_model": _cpu_model()}
     print(json.dumps(res))
 
 
