@@ -273,10 +273,12 @@ __device__ __forceinline__ const T *opaque_ptr(const T *p) {
 // without branches ahead of their use (rows e >= d repeat row d-1 and are unused).
 template <int D>
 __device__ __forceinline__ void load_meta(uint32_t *m, const uint32_t *edge_meta, int off, int d, int lane) {
-    const auto mp = as_global(edge_meta) + off + lane;
-    const int last = max(d, 1) - 1;
+    const int last = max(d, 1) - 1;  // off and d are wave-uniform: each row address is scalar
 #pragma unroll
-    for (int e = 0; e < D; ++e) m[e] = mp[min(e, last) * kWave];
+    for (int e = 0; e < D; ++e) {
+        const auto row = as_global(edge_meta) + __builtin_amdgcn_readfirstlane(off + min(e, last) * kWave);
+        m[e] = row[lane];
+    }
 }
 
 template <int DMIN, int DMAX, typename F>
