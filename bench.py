@@ -671,6 +671,17 @@ def main():
         res["plain"] = {"mbit_s": round(len(sample) * H.n / pt / 1e6, 3), "frames": int(len(sample)),
                         "form": "streamed, batch of 1", "mean_iterations": round(float(pit.mean()), 1),
                         "batched_over_plain": round(value / (len(sample) * H.n / pt / 1e6), 1)}
+        # one frame per launch without per-iteration launches: the resident form on a
+        # batch of one (a single workgroup decodes the frame to completion)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, f in enumerate(sample):
+            lp.decode(code, llr[f:f + 1], out=one[k], mode=lp.MODE_RESIDENT, **P)
+        torch.cuda.synchronize()
+        rt = time.perf_counter() - t0
+        res["plain_resident"] = {"mbit_s": round(len(sample) * H.n / rt / 1e6, 3), "frames": int(len(sample)),
+                                 "form": "resident, batch of 1",
+                                 "batched_over_plain": round(value / (len(sample) * H.n / rt / 1e6), 1)}
 
     if args.serving_seconds > 0 and not args.no_extra:
         res["serving"] = run_serving(lp, W, args.serving_seconds)
