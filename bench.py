@@ -130,6 +130,12 @@ def run_serving(lp, W, seconds: float, seed: int = 0, budget_bytes: int = 512 <<
     srv.close()
     lat = np.array(lat)
     bits = sum(r.frames * Hs[r.code].n for r in trace)
+    by_code = {}
+    for c, H in enumerate(Hs):
+        lc = np.array([lat[i] for i, r in enumerate(trace) if r.code == c])
+        if lc.size:
+            by_code[str(H.n)] = {"requests": int(lc.size), "p50_ms": round(float(np.percentile(lc, 50)) * 1e3, 2),
+                                 "p99_ms": round(float(np.percentile(lc, 99)) * 1e3, 2)}
     return {
         "requests": len(trace), "frames": int(sum(r.frames for r in trace)), "trace_seconds": seconds,
         "offered_mbit_s": round(bits / seconds / 1e6, 1), "delivered_mbit_s": round(bits / wall / 1e6, 1),
@@ -137,7 +143,7 @@ def run_serving(lp, W, seconds: float, seed: int = 0, budget_bytes: int = 512 <<
         "p99_latency_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
         "max_latency_ms": round(float(lat.max()) * 1e3, 3),
         "peak_admitted_bytes": int(st["peak_bytes"]), "budget_bytes": budget_bytes,
-        "launches": int(st["launches"] - base["launches"]),
+        "launches": int(st["launches"] - base["launches"]), "latency_by_code_n": by_code,
     }
 
 
