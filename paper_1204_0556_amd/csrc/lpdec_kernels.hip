@@ -259,6 +259,10 @@ template <typename T>
 __device__ __forceinline__ const __attribute__((address_space(1))) T *as_global(const T *p) {
     return (const __attribute__((address_space(1))) T *)p;
 }
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *as_global_rw(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
 
 // The same pointer, hidden from the optimiser (loads through it are not moved
 // out of the loop they are written in).
@@ -266,6 +270,18 @@ template <typename T>
 __device__ __forceinline__ const T *opaque_ptr(const T *p) {
     asm volatile("" : "+s"(p));
     return p;
+}
+
+// Degree, offset and check count of chunk c (c wave-uniform).
+struct ChunkDesc {
+    int deg, off, cnt;
+};
+__device__ __forceinline__ ChunkDesc chunk_desc(const DevCode &C, int c) {
+    ChunkDesc h;
+    h.deg = __builtin_amdgcn_readfirstlane(as_global(C.chunk_deg)[c]);
+    h.off = __builtin_amdgcn_readfirstlane(as_global(C.chunk_off)[c]);
+    h.cnt = __builtin_amdgcn_readfirstlane(as_global(C.chunk_cnt)[c]);
+    return h;
 }
 
 // Packed metadata of one chunk of degree d (0: no chunk) into m[0..D): loads for
@@ -357,13 +373,13 @@ __device__ __forceinline__ void check_update(float *z, float *u, const uint32_t 
 
 template <bool HALF>
 __device__ __forceinline__ float ld_state(const void *p, size_t i) {
-    if constexpr (HALF) return __half2float(static_cast<const __half *>(p)[i]);
-    else return static_cast<const float *>(p)[i];
+    if constexpr (HALF) return __half2float(__ushort_as_half(as_global(static_cast<const unsigned short *>(p))[i]));
+    else return as_global(static_cast<const float *>(p))[i];
 }
 template <bool HALF>
 __device__ __forceinline__ void st_state(void *p, size_t i, float a) {
-    if constexpr (HALF) static_cast<__half *>(p)[i] = __float2half_rn(a);
-    else static_cast<float *>(p)[i] = a;
+    if constexpr (HALF) as_global_rw(static_cast<unsigned short *>(p))[i] = __half_as_ushort(__float2half_rn(a));
+    else as_global_rw(static_cast<float *>(p))[i] = a;
 }
 
 // ---------------------------------------------------------------------------
@@ -409,7 +425,10 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
-    const int wave = tid >> 6;
+    // the wave index in a scalar register lets the chunk walks use scalar
+    // arithmetic; the degree 6..8 resident kernel, short of scalar registers
+    // already, keeps it in a vector register
+    const int wave = (RES && DMAX > 6) ? (tid >> 6) : __builtin_amdgcn_readfirstlane(tid >> 6);
     const int NT = blockDim.x;
     const int NW = NT >> 6;
 
@@ -534,9 +553,10 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 for (int k = 0; k < CPT; ++k) {
                     const int c = wave + k * C.waves;
                     const bool has = (wave < C.waves) && (k < C.cpt) && (c < C.nchunks);
-                    cdeg[k] = has ? __builtin_amdgcn_readfirstlane(C.chunk_deg[c]) : 0;
-                    coff[k] = has ? __builtin_amdgcn_readfirstlane(C.chunk_off[c]) : 0;
-                    cval[k] = has && (lane < C.chunk_cnt[c]);
+                    const ChunkDesc h = has ? chunk_desc(C, c) : ChunkDesc{0, 0, 0};
+                    cdeg[k] = h.deg;
+                    coff[k] = h.off;
+                    cval[k] = lane < h.cnt;
                     if constexpr (MREG) {
 #pragma unroll
                         for (int e = 0; e < DMAX; ++e)
@@ -623,8 +643,9 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                     }
             } else {
                 for (int c = wave; c < C.nchunks && wave < C.waves; c += C.waves) {
-                    const int d = C.chunk_deg[c], off = C.chunk_off[c];
-                    const bool lv = lane < C.chunk_cnt[c];
+                    const ChunkDesc h = chunk_desc(C, c);
+                    const int d = h.deg, off = h.off;
+                    const bool lv = lane < h.cnt;
                     for (int e = 0; e < d; ++e) {
                         const int p = off + e * kWave + lane;
                         float z0 = 0.0f, u0 = 0.0f;
@@ -690,13 +711,15 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 }
             } else {
                 for (int c = wave; c < C.nchunks && wave < C.waves; c += C.waves) {
-                    const int d = C.chunk_deg[c], off = C.chunk_off[c];
-                    if (lane < C.chunk_cnt[c]) {
+                    const ChunkDesc h = chunk_desc(C, c);
+                    const int d = h.deg, off = h.off;
+                    if (lane < h.cnt) {
                         for (int e = 0; e < d; ++e) {
                             const size_t p = off + e * kWave + lane;
                             const float w = ld_state<HALF>(gz, p) - ld_state<HALF>(gu, p);
-                            if constexpr (SM == 2) atomicAdd(acc + (C.edge_meta[p] & 0xffffu), to_fixed(w));
-                            else slots[C.edge_meta[p] >> 16] = w;
+                            const uint32_t mt = as_global(C.edge_meta)[p];
+                            if constexpr (SM == 2) atomicAdd(acc + (mt & 0xffffu), to_fixed(w));
+                            else slots[mt >> 16] = w;
                         }
                     }
                 }
@@ -726,12 +749,13 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 const float *gsrc = C.var_identity ? gam : gmu_row;
                 const float gscale = C.var_identity ? ip.mu_inv : 1.0f;
                 for (int i = tid; i < C.n; i += NT) {
-                    const unsigned prev = xprev ? xprev[i] : 0u;
+                    const unsigned prev = xprev ? as_global(xprev)[i] : 0u;
                     const unsigned long long a = acc[i] - ((unsigned long long)prev << 32);
-                    const float inv = (C.dv > 0) ? C.dv_inv : __int_as_float(C.var_info[i].y);
+                    const float inv = (C.dv > 0) ? C.dv_inv
+                                                 : __int_as_float(as_global(reinterpret_cast<const int *>(C.var_info))[2 * i + 1]);
                     const float x = clamp01((from_fixed(a) - gsrc[i] * gscale) * inv);
                     acc[i] = (unsigned long long)__float_as_uint(x) << 32;
-                    if (xprev) xprev[i] = __float_as_uint(x);
+                    if (xprev) as_global_rw(xprev)[i] = __float_as_uint(x);
                 }
             } else {
                 // gamma/mu: straight from the frame's LLRs when variables keep their
@@ -845,9 +869,9 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 }
             } else {
                 for (int c = wave; c < C.nchunks && wave < C.waves; c += C.waves) {
-                    const int d = __builtin_amdgcn_readfirstlane(C.chunk_deg[c]);
-                    const int off = C.chunk_off[c];
-                    if (lane < C.chunk_cnt[c]) {
+                    const ChunkDesc h = chunk_desc(C, c);
+                    const int d = h.deg, off = h.off;
+                    if (lane < h.cnt) {
                         dispatch_degree<DMIN, DMAX>(d, [&](auto dc) {
                             constexpr int D = decltype(dc)::value;
                             float zz[D], uu[D];
@@ -857,7 +881,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                                 const size_t p = off + e * kWave + lane;
                                 zz[e] = ld_state<HALF>(gz, p);
                                 uu[e] = ld_state<HALF>(gu, p);
-                                mm[e] = C.edge_meta[p];
+                                mm[e] = as_global(C.edge_meta)[p];
                             }
                             check_update<D, XS>(zz, uu, mm, xs, ip.rho, rp, rd);
 #pragma unroll
@@ -968,8 +992,9 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         }
         bool odd = false;
         for (int c = wave; c < C.nchunks && wave < C.waves; c += C.waves) {
-            const int d = C.chunk_deg[c], off = C.chunk_off[c];
-            if (lane < C.chunk_cnt[c]) {
+            const ChunkDesc h = chunk_desc(C, c);
+            const int d = h.deg, off = h.off;
+            if (lane < h.cnt) {
                 bool par = false;
                 for (int e = 0; e < d; ++e)
                     par ^= (xs[XS * (C.edge_meta[off + e * kWave + lane] & 0xffffu)] >= 0.5f);
@@ -1008,8 +1033,9 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                         }
             } else {
                 for (int c = wave; c < C.nchunks && wave < C.waves; c += C.waves) {
-                    const int d = C.chunk_deg[c], off = C.chunk_off[c];
-                    if (lane < C.chunk_cnt[c]) {
+                    const ChunkDesc h = chunk_desc(C, c);
+                    const int d = h.deg, off = h.off;
+                    if (lane < h.cnt) {
                         for (int e = 0; e < d; ++e) {
                             const size_t p = off + e * kWave + lane;
                             const int ce = C.edge_csr[p];
