@@ -52,7 +52,8 @@ k_dual(const DevCode *__restrict__ codes, FrameBatch fb, double mu, int max_iter
     extern __shared__ __attribute__((aligned(16))) int dlds[];
     __shared__ int s_frame;
     const DevCode &C = codes[0];
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid >> 6, NT = blockDim.x;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), NT = blockDim.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     int *S = dlds;
     float *ng = reinterpret_cast<float *>(dlds + C.n);
     uint8_t *xb = reinterpret_cast<uint8_t *>(dlds + 2 * C.n);
@@ -60,15 +61,15 @@ k_dual(const DevCode *__restrict__ codes, FrameBatch fb, double mu, int max_iter
     // this lane's checks: chunk c = wave + k * waves; their edge metadata is
     // re-read from the (cache-resident) code table rather than held in registers
     int cdeg[CPT];
-    const uint32_t *cmeta[CPT];
+    const __attribute__((address_space(1))) uint32_t *cmeta[CPT];
     bool cval[CPT];
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
         const int c = wave + k * C.waves;
         const bool has = (wave < C.waves) && (k < C.cpt) && (c < C.nchunks);
-        cdeg[k] = has ? C.chunk_deg[c] : 0;
-        cmeta[k] = C.edge_meta + (has ? C.chunk_off[c] : 0) + lane;
-        cval[k] = has && (lane < C.chunk_cnt[c]);
+        cdeg[k] = has ? __builtin_amdgcn_readfirstlane(as_global(C.chunk_deg)[c]) : 0;
+        cmeta[k] = as_global(C.edge_meta) + (has ? __builtin_amdgcn_readfirstlane(as_global(C.chunk_off)[c]) : 0) + lane;
+        cval[k] = has && (lane < as_global(C.chunk_cnt)[c]);
     }
 
     // Workgroup-uniform values (the frame index, the outcome of a workgroup

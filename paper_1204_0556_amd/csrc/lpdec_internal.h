@@ -15,6 +15,18 @@ constexpr int kStageEdges = 8192;
 constexpr int kStageVars = 4096;
 constexpr int kMaxD = 8;           // LPDEC_MAX_CHECK_DEGREE
 
+// A pointer read from memory (a code table, an argument structure) is generic to
+// the compiler, and a generic load also waits on LDS traffic; these mark one as
+// pointing to global memory.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *as_global(const T *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *as_global_rw(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // Device view of one code (all pointers are device memory owned by the code).
 //
 // Checks are grouped by degree and cut into "chunks" of up to 64 checks of one

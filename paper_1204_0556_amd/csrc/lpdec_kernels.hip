@@ -252,17 +252,6 @@ __device__ __forceinline__ void lds_copy4(const float *src, float *lds_base) {
     __builtin_amdgcn_global_load_lds(src, lds_base, 4, 0, 0);
 }
 
-// A pointer read from a kernel argument structure is generic to the compiler,
-// and a generic load waits on LDS traffic as well; this one is known to point to
-// global memory.
-template <typename T>
-__device__ __forceinline__ const __attribute__((address_space(1))) T *as_global(const T *p) {
-    return (const __attribute__((address_space(1))) T *)p;
-}
-template <typename T>
-__device__ __forceinline__ __attribute__((address_space(1))) T *as_global_rw(T *p) {
-    return (__attribute__((address_space(1))) T *)p;
-}
 
 // The same pointer, hidden from the optimiser (loads through it are not moved
 // out of the loop they are written in).
