@@ -701,14 +701,34 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             } else {
                 for (int c = wave; c < C.nchunks && wave < C.waves; c += C.waves) {
                     const ChunkDesc h = chunk_desc(C, c);
-                    const int d = h.deg, off = h.off;
                     if (lane < h.cnt) {
-                        for (int e = 0; e < d; ++e) {
-                            const size_t p = off + e * kWave + lane;
-                            const float w = ld_state<HALF>(gz, p) - ld_state<HALF>(gu, p);
-                            const uint32_t mt = as_global(C.edge_meta)[p];
-                            if constexpr (SM == 2) atomicAdd(acc + (mt & 0xffffu), to_fixed(w));
-                            else slots[mt >> 16] = w;
+                        if constexpr (DMIN == DMAX || !PERSIST) {
+                            // the degree as a constant: all of the chunk's loads are
+                            // issued before the first is used
+                            dispatch_degree<DMIN, DMAX>(h.deg, [&](auto dc) {
+                                constexpr int D = decltype(dc)::value;
+                                float w[D];
+                                uint32_t mt[D];
+#pragma unroll
+                                for (int e = 0; e < D; ++e) {
+                                    const size_t p = h.off + e * kWave + lane;
+                                    w[e] = ld_state<HALF>(gz, p) - ld_state<HALF>(gu, p);
+                                    mt[e] = as_global(C.edge_meta)[p];
+                                }
+#pragma unroll
+                                for (int e = 0; e < D; ++e) {
+                                    if constexpr (SM == 2) atomicAdd(acc + (mt[e] & 0xffffu), to_fixed(w[e]));
+                                    else slots[mt[e] >> 16] = w[e];
+                                }
+                            });
+                        } else {  // persistent 2..8 kernel: the seven copies measured slower
+                            for (int e = 0; e < h.deg; ++e) {
+                                const size_t p = h.off + e * kWave + lane;
+                                const float w = ld_state<HALF>(gz, p) - ld_state<HALF>(gu, p);
+                                const uint32_t mt = as_global(C.edge_meta)[p];
+                                if constexpr (SM == 2) atomicAdd(acc + (mt & 0xffffu), to_fixed(w));
+                                else slots[mt >> 16] = w;
+                            }
                         }
                     }
                 }
