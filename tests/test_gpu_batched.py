@@ -147,3 +147,35 @@ def test_largest_codes_use_global_slots():
         outs.append((x, z, u))
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+def test_uneven_batch_full_size_sampled():
+    """The full 16384-frame uneven batch in the launch the benchmark times (one
+    decode_multi call); a sample of frames of every code is checked against the
+    oracle, and every frame's flags against a host recomputation."""
+    codes_h = [W.irregular_half(n) for n in W.IRREGULAR_LENGTHS]
+    batch = W.mixed_batch(codes_h, 16384, 1.5, 3.0, tag="uneven")
+    flat, off = batch.flat_llr()
+    handles = [lp.Code(H) for H in codes_h]
+    print(f"uneven full batch frames={batch.frames}", flush=True)
+    x, it, fl = lp.decode_multi(handles, batch.code_of_frame, off, dev(flat), off, flat.size, **W.PAPER_PARAMS)
+    x, it, fl = host(x), host(it), host(fl)
+    rng = np.random.default_rng(5)
+    for c, H in enumerate(codes_h):
+        idx = np.nonzero(batch.code_of_frame == c)[0]
+        pick = rng.choice(idx, 8, replace=False)
+        llr = np.stack([batch.llr[f] for f in pick])
+        ref = oracle.decode(H, llr, **W.PAPER_PARAMS)
+        Hd = H.to_scipy()
+        for k, f in enumerate(pick):
+            xg = x[off[f]:off[f] + H.n]
+            ambiguous = np.any(np.abs(ref.x[k] - 0.5) < 1e-3)
+            assert ambiguous or np.array_equal(xg >= 0.5, ref.x[k] >= 0.5), (H.n, f)
+            assert ambiguous or abs(int(it[f]) - int(ref.iters[k])) <= 2, (H.n, f, it[f], ref.iters[k])
+        # flags of every frame of this code against the certificate recomputed here
+        for f in idx[:512]:
+            xg = x[off[f]:off[f] + H.n]
+            hard = (xg >= 0.5).astype(np.int64)
+            codeword = not np.any((Hd @ hard) % 2)
+            integral = np.max(np.minimum(xg, 1 - xg)) <= 1e-3
+            assert codeword == bool(fl[f] & 0x04) and integral == bool(fl[f] & 0x02)
