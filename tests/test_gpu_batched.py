@@ -179,3 +179,27 @@ def test_uneven_batch_full_size_sampled():
             codeword = not np.any((Hd @ hard) % 2)
             integral = np.max(np.minimum(xg, 1 - xg)) <= 1e-3
             assert codeword == bool(fl[f] & 0x04) and integral == bool(fl[f] & 0x02)
+
+
+@pytest.mark.parametrize("which", ["36", "48"])
+def test_precision_batch_full_size_sampled(which):
+    """The 8192-frame n = 16384 batches of the precision study in the launch the
+    benchmark times (streamed form, FP32 and FP16 storage): sampled frames against
+    the oracle, and FP16 hard decisions against FP32 on every frame."""
+    H = W.gallager36(16384) if which == "36" else W.gallager48(16384)
+    llr_h = W.awgn_batch(H, 8192, 2.5, tag="precision")
+    code = lp.Code(H)
+    print(f"precision batch ({which}) frames=8192", flush=True)
+    out = {}
+    for st in (lp.STORAGE_FP32, lp.STORAGE_FP16):
+        x, it, fl = lp.decode(code, dev(llr_h), mode=lp.MODE_STREAMED, storage=st, **W.PAPER_PARAMS)
+        out[st] = (host(x), host(it), host(fl))
+    pick = np.random.default_rng(7).choice(8192, 6, replace=False)
+    ref = oracle.decode(H, llr_h[pick], **W.PAPER_PARAMS)
+    x32, it32, _ = out[lp.STORAGE_FP32]
+    for k, f in enumerate(pick):
+        ambiguous = np.any(np.abs(ref.x[k] - 0.5) < 1e-3)
+        assert ambiguous or np.array_equal(x32[f] >= 0.5, ref.x[k] >= 0.5)
+        assert ambiguous or abs(int(it32[f]) - int(ref.iters[k])) <= 2
+    agree = np.all((x32 >= 0.5) == (out[lp.STORAGE_FP16][0] >= 0.5), axis=1)
+    assert agree.mean() >= 0.999
