@@ -143,6 +143,12 @@ def test_small_code_end_to_end():
     fer_gpu = np.mean(host(x).__ge__(0.5).any(axis=1))
     fer_cpu = np.mean(ref.hard.any(axis=1))
     assert abs(fer_gpu - fer_cpu) <= 0.005
+    # the GPU FER lies inside the oracle's 95 % Clopper-Pearson interval
+    from scipy.stats import beta
+    k, N = int(round(fer_cpu * len(llr))), len(llr)
+    lo = beta.ppf(0.025, k, N - k + 1) if k > 0 else 0.0
+    hi = beta.ppf(0.975, k + 1, N - k) if k < N else 1.0
+    assert lo <= fer_gpu <= hi, (fer_gpu, lo, hi)
 
 
 def test_headline_batch_sampled():
