@@ -172,6 +172,17 @@ def test_headline_batch_sampled():
     integral = np.max(np.minimum(x, 1 - x), axis=1) <= 1e-3
     assert np.array_equal(integral, (fl & 0x02) != 0)
     assert np.all(it[(fl & 0x01) == 0] == 1000)
+    # FER at each Eb/N0 (all 4096 frames) inside the 95 % Clopper-Pearson interval of
+    # the oracle's FER on the first 1024 frames of that block
+    from scipy.stats import beta
+    for b in range(4):
+        blk = slice(b * 4096, b * 4096 + 1024)
+        ref_b = oracle.decode(H, llr[blk])
+        k, N = int(ref_b.hard.any(axis=1).sum()), 1024
+        lo = beta.ppf(0.025, k, N - k + 1) if k > 0 else 0.0
+        hi = beta.ppf(0.975, k + 1, N - k) if k < N else 1.0
+        fer = float((x[b * 4096:(b + 1) * 4096] >= 0.5).any(axis=1).mean())
+        assert lo <= fer <= hi, (W.HEADLINE_SNRS[b], fer, lo, hi)
 
 
 def test_invalid_frames_are_flagged():
