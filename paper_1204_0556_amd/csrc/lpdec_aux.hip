@@ -58,10 +58,13 @@ k_dual(const DevCode *__restrict__ codes, FrameBatch fb, double mu, int max_iter
     float *ng = reinterpret_cast<float *>(dlds + C.n);
     uint8_t *xb = reinterpret_cast<uint8_t *>(dlds + 2 * C.n);
 
-    // this lane's checks: chunk c = wave + k * waves; their edge metadata is
-    // re-read from the (cache-resident) code table rather than held in registers
+    // this lane's checks: chunk c = wave + k * waves; their edge metadata is held
+    // in registers when it fits (up to 32 entries per lane), else re-read from the
+    // (cache-resident) code table
+    constexpr bool MREG = CPT * DMAX <= 32;
     int cdeg[CPT];
     const __attribute__((address_space(1))) uint32_t *cmeta[CPT];
+    uint32_t cm[MREG ? CPT : 1][MREG ? DMAX : 1];
     bool cval[CPT];
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
@@ -70,6 +73,10 @@ k_dual(const DevCode *__restrict__ codes, FrameBatch fb, double mu, int max_iter
         cdeg[k] = has ? __builtin_amdgcn_readfirstlane(as_global(C.chunk_deg)[c]) : 0;
         cmeta[k] = as_global(C.edge_meta) + (has ? __builtin_amdgcn_readfirstlane(as_global(C.chunk_off)[c]) : 0) + lane;
         cval[k] = has && (lane < as_global(C.chunk_cnt)[c]);
+        if constexpr (MREG) {
+#pragma unroll
+            for (int e = 0; e < DMAX; ++e) cm[k][e] = (cval[k] && e < cdeg[k]) ? cmeta[k][e * kWave] : 0u;
+        }
     }
 
     // Workgroup-uniform values (the frame index, the outcome of a workgroup
@@ -146,7 +153,7 @@ k_dual(const DevCode *__restrict__ codes, FrameBatch fb, double mu, int max_iter
                             int z = K[k][e] > 0 ? 1 : 0;
                             if (odd && e == ip && !add_n) z = 0;
                             if (add_n && e == in) z = 1;
-                            const int var = (int)(cmeta[k][e * kWave] & 0xffffu);
+                            const int var = (int)((MREG ? cm[k][MREG ? e : 0] : cmeta[k][e * kWave]) & 0xffffu);
                             const int delta = (int)xb[var] - z;
                             if (delta != 0) {
                                 K[k][e] += delta;
