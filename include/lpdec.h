@@ -148,9 +148,10 @@ lpdec_status lpdec_decode_state(const lpdec_code *code, int32_t batch, const flo
  * Offsets are checked against llr_len / x_len (elements).  A frame's result does
  * not depend on the other frames of the batch.  When the codes differ in size,
  * the launch hands out frames of larger codes first (processing order only).
- * Resident form (LPDEC_MODE_RESIDENT / AUTO): all codes with check degree 6, or
- * all with check degrees in 6..8; otherwise the persistent-global form.  FP16
- * storage and the streamed form are not available here (LPDEC_EUNSUPPORTED). */
+ * AUTO picks the register-resident form when every code's checks have degree 6
+ * (or all lie in 6..8) and the largest code fits its register and LDS budget,
+ * else the persistent-global form.  FP16 storage and the streamed form are not
+ * available here (LPDEC_EUNSUPPORTED). */
 lpdec_status lpdec_decode_multi(const lpdec_code *const *codes, int32_t ncodes, int32_t nframes,
                                 const int32_t *code_of_frame, const int64_t *llr_offset,
                                 const float *llr, int64_t llr_len, const lpdec_params *p,
