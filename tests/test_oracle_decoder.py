@@ -210,3 +210,51 @@ def test_small_config_reference_run_against_exact_lp():
             assert abs(g @ res.x[f] - lp) < 1e-3 * (1 + abs(lp))
         if res.flags[f] & oracle.FLAG_CERTIFIED:
             assert np.array_equal(res.hard[f], (xlp > 0.5).astype(np.uint8))
+
+
+def mixed_degree_code(seed):
+    """n = 24, m = 12 with variable degrees 2, 3 and 6 (6, 12 and 6 columns) and
+    every check degree in [2, 8]: nnz = 84, mean check degree 7."""
+    rng = np.random.default_rng([24, 12, seed])
+    degs = np.array([2] * 6 + [3] * 12 + [6] * 6)
+    while True:
+        Hd = np.zeros((12, 24), np.uint8)
+        for i, d in enumerate(degs):
+            Hd[rng.choice(12, d, replace=False), i] = 1
+        if Hd.sum(1).min() >= 2 and Hd.sum(1).max() <= 8:
+            break
+    rows, cols = np.nonzero(Hd)
+    row_ptr = np.zeros(13, np.int32)
+    np.cumsum(np.bincount(rows, minlength=12), out=row_ptr[1:])
+    return W.ParityCheckMatrix(12, 24, row_ptr, cols.astype(np.int32), f"mixed24 seed={seed}")
+
+
+def test_x_update_with_mixed_variable_degrees():
+    # each variable averages over its own |N_v(i)| replicas (Sec. 3.2): the returned x
+    # is the coordinate-wise argmin of L_mu over the box for degrees 2, 3 and 6 alike
+    H = mixed_degree_code(0)
+    assert set(np.bincount(H.col_idx, minlength=H.n)) == {2, 3, 6}
+    rng = np.random.default_rng(4)
+    mu = 3.0
+    gamma = rng.normal(0.8, 2.0, (1, H.n)).astype(np.float32)
+    z0 = rng.uniform(0, 1, (1, H.nnz))
+    u0 = rng.normal(0, 0.5, (1, H.nnz))
+    res = oracle.decode(H, gamma, mu=mu, rho=1.0, max_iter=1, tol=0.0, z0=z0, u0=u0)
+    for i in range(H.n):
+        edges = np.nonzero(H.col_idx == i)[0]
+        want = pins.lagrangian_x_argmin(float(gamma[0, i]), z0[0, edges], mu * u0[0, edges], mu)
+        assert abs(res.x[0, i] - want) < 1e-7
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_fixed_point_is_the_lp_optimum_mixed_degrees(seed):
+    # checks of degree up to 8 and variables of degree 2, 3 and 6: the over-relaxed
+    # iteration still converges to the optimum of the LP relaxation
+    H = mixed_degree_code(seed)
+    rng = np.random.default_rng([seed, 11])
+    gamma = rng.normal(1.0, 1.5, (3, H.n)).astype(np.float32)
+    res = oracle.decode(H, gamma, mu=3.0, rho=1.9, max_iter=20000, tol=1e-10)
+    for f in range(gamma.shape[0]):
+        g = gamma[f].astype(np.float64)
+        lp, _ = pins.feldman_lp(H.row_ptr, H.col_idx, H.n, g)
+        assert abs(g @ res.x[f] - lp) < 1e-6 * (1 + abs(lp)), (f, g @ res.x[f], lp, res.iters[f])
