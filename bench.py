@@ -99,7 +99,7 @@ def run_serving(lp, W, seconds: float, seed: int = 0, budget_bytes: int = 512 <<
           W.gallager36(16384)]
     codes = [lp.Code(H) for H in Hs]
     trace = W.serving_trace(Hs, duration_s=seconds, frames_per_s=50_000.0, max_frames=256, seed=seed)
-    srv = lp.Server(codes, budget_bytes=budget_bytes, max_batch_frames=4096, max_inflight=4)
+    srv = lp.Server(codes, budget_bytes=budget_bytes, max_batch_frames=4096, max_inflight=8)
     # warm the kernels (module load, first-launch costs) outside the measurement
     for c, H in enumerate(Hs):
         srv.wait(srv.submit(c, W.awgn_batch(H, 2, 3.0, tag="warm")), timeout=120.0)

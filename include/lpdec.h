@@ -283,7 +283,7 @@ typedef struct lpdec_server lpdec_server;
 typedef struct {
     int64_t budget_bytes;     /* device bytes for admitted frames (> 0)                 */
     int32_t max_batch_frames; /* frames per launch (>= 1)                               */
-    int32_t max_inflight;     /* launches in flight at once (1..8)                      */
+    int32_t max_inflight;     /* launches in flight at once (1..8; default 8)           */
     int32_t max_pending;      /* queued requests before submit returns LPDEC_EBUSY      */
     int32_t executor;         /* LPDEC_EXECUTOR_*                                       */
 } lpdec_server_config;

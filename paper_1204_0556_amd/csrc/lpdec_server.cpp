@@ -319,7 +319,7 @@ lpdec_server_config lpdec_server_default_config(void) {
     lpdec_server_config c;
     c.budget_bytes = (int64_t)256 << 20;
     c.max_batch_frames = 4096;
-    c.max_inflight = 4;
+    c.max_inflight = 8;
     c.max_pending = 1 << 16;
     c.executor = LPDEC_EXECUTOR_GPU;
     return c;
