@@ -58,7 +58,9 @@ typedef enum {
 /* Execution form. */
 #define LPDEC_MODE_AUTO 0     /* fastest form that fits the code                       */
 #define LPDEC_MODE_RESIDENT 1 /* one persistent launch; a workgroup keeps a frame's
-                                 replicas and duals in registers until it converges    */
+                                 replicas and duals in registers until it converges
+                                 (codes whose checks all have degree 6, or all degrees
+                                 6..8, and whose state fits; see resident_capable)     */
 #define LPDEC_MODE_STREAMED 2 /* replicas and duals live in HBM; one launch per
                                  iteration over all unfinished frames                  */
 #define LPDEC_MODE_PERSISTENT_GLOBAL 3 /* one persistent launch; per-workgroup state in
