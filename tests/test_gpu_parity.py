@@ -211,6 +211,27 @@ def test_warm_start_resume_is_exact():
         assert np.array_equal(host(a[0]), host(c[0]))
 
 
+@pytest.mark.parametrize("n,mode,storage", [(2640, "pglobal", 0), (16384, "pglobal", 0), (16384, "streamed", 0),
+                                            (16384, "streamed", 1)])
+def test_warm_start_resume_is_exact_in_every_form(n, mode, storage):
+    # 12 + 18 iterations from the exported state equal 30 in one go, bitwise: the
+    # persistent-global form with LDS float slots (n = 2640) and with LDS fixed-point
+    # accumulators (n = 16384), the streamed form with FP32 and FP16 state storage
+    # (FP16 values export to FP32 exactly and load back exactly)
+    H = W.gallager36(n)
+    llr = W.awgn_batch(H, 3, 1.5, tag="warm-forms")
+    code = lp.Code(H)
+    m = {"pglobal": lp.MODE_PERSISTENT_GLOBAL, "streamed": lp.MODE_STREAMED}[mode]
+    kw = dict(tol=0.0, mode=m, storage=storage)
+    print(f"warm start n={n} {mode} storage={storage}", flush=True)
+    a = lp.decode_state(code, dev(llr), max_iter=30, **kw)
+    b = lp.decode_state(code, dev(llr), max_iter=12, **kw)
+    c = lp.decode_state(code, dev(llr), z=b[3], u=b[4], state_in=True, max_iter=18, **kw)
+    assert np.array_equal(host(a[3]), host(c[3])) and np.array_equal(host(a[4]), host(c[4]))
+    assert np.array_equal(host(a[0]), host(c[0]))
+    assert np.all(host(c[1]) == 18)
+
+
 def test_edge_batches():
     H = W.gallager36(96)
     code = lp.Code(H)
