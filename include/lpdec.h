@@ -223,7 +223,15 @@ typedef struct {
     int32_t variant;               /* streamed form: 0 z,u re-read from HBM in each phase;
                                       1 two chunks per wave in registers, two workgroups
                                       per CU; 2 as 1 with one workgroup per CU staging the
-                                      next frame in LDS (direct-to-LDS loads); -1 other forms */
+                                      next frame in LDS (direct-to-LDS loads).
+                                      resident form, for one code whose checks all have
+                                      degree 6 and variables degree 3, planned with two
+                                      chunks per wave: 0 one frame per workgroup; 1 two
+                                      frames per 12-wave workgroup, placed so that the
+                                      SIMDs of a CU hold even shares of the chunks (the
+                                      default where that shortens the check phase, for
+                                      batches of at least two frames per CU; smaller
+                                      batches run variant 0).  -1 otherwise             */
 } lpdec_launch_info;
 
 /* The launch a decode of `code` with parameters `p` (NULL = defaults; mode and
@@ -234,24 +242,28 @@ lpdec_status lpdec_code_launch_info(const lpdec_code *code, const lpdec_params *
 /* Fix the launch of one form (LPDEC_MODE_RESIDENT, _STREAMED or
  * _PERSISTENT_GLOBAL) for this code.
  *   blocks_per_cu  workgroups per CU, 1..32; 0 restores the runtime's estimate
- *   variant        streamed form only (see lpdec_launch_info.variant): 0, 1 or 2;
- *                  a variant the code does not allow falls back to the next
- *                  lower one; -1 restores the default (the highest allowed).
- *                  Ignored by the other forms.
+ *   variant        see lpdec_launch_info.variant.  Streamed form: 0, 1 or 2; a
+ *                  variant the code does not allow falls back to the next lower
+ *                  one; -1 restores the default (the highest allowed).  Resident
+ *                  form: 0 or 1 (1 falls back to 0 where the code does not allow
+ *                  two frames per workgroup, and is then used for every batch
+ *                  size); -1 restores the default.  Ignored by the
+ *                  persistent-global form.
  * Not synchronised with decodes running on other threads. */
 lpdec_status lpdec_code_set_tuning(lpdec_code *code, int32_t mode, int32_t blocks_per_cu,
                                    int32_t variant);
 
 /* Autotuner: decode the caller's sample batch (device llr [batch*n]) with
  * parameters `p` once per candidate launch -- workgroups per CU 1..max_blocks_per_cu,
- * times the variants 0, 1, 2 the code allows for the streamed form -- after one
+ * times the variants the code allows (streamed form: 0, 1, 2; resident form: 0, 1
+ * where two frames per workgroup are possible) -- after one
  * untimed warm-up decode, time each with HIP events on `stream`, and keep the
  * fastest for the form `p` resolves to.  Synchronous.
  *   best_out  host [2], may be NULL: the chosen blocks_per_cu and variant (-1
  *             for forms without variants)
  *   ms_out    host [3*max_blocks_per_cu], may be NULL: time of candidate
- *             (variant v, blocks b) at [v*max_blocks_per_cu + b - 1] (streamed
- *             form), or at [b - 1] (other forms); -1 where not run
+ *             (variant v, blocks b) at [v*max_blocks_per_cu + b - 1] (forms with
+ *             variants), or at [b - 1] (others); -1 where not run
  * Scratch outputs are allocated and freed inside the call. */
 lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, const lpdec_params *p,
                             int32_t max_blocks_per_cu, int32_t *best_out, float *ms_out, void *stream);

@@ -237,12 +237,12 @@ class Code:
         ms = (ctypes.c_float * (3 * mb))()
         _check(_lib.lpdec_autotune(self.handle, B, _dev_ptr(llr, torch.float32, "llr"), ctypes.byref(p),
                                    mb, best, ms, _stream(stream)))
-        streamed = self.launch_info(**params)["mode"] == MODE_STREAMED
+        # entries of variant v at [v * mb + b]; forms without variants use v = 0 and report -1
         times = {}
-        for v in range(3 if streamed else 1):
+        for v in range(3):
             for b in range(mb):
                 if ms[v * mb + b] >= 0:
-                    times[(v if streamed else -1, b + 1)] = float(ms[v * mb + b])
+                    times[(v if best[1] >= 0 else -1, b + 1)] = float(ms[v * mb + b])
         return (best[0], best[1]), times
 
     def close(self):

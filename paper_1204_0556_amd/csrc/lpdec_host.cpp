@@ -249,6 +249,7 @@ lpdec_status build_plan(int32_t m, int32_t n, int64_t nnz, const int32_t *row_pt
 
 // Launch-shape planning for a set of codes decoded together.
 struct Shape {
+    int ncodes = 0, nchunks = 0;
     int waves = 0, cpt = 0, nmax = 0, Emax = 0, Eint_max = 0, dclass = 0;
     int dv = 0;  // common variable degree of all codes (0 if mixed)
     bool permuted = false;  // some code renumbers its variables
@@ -256,9 +257,11 @@ struct Shape {
 
 Shape shape_of(const lpdec_code *const *codes, int ncodes) {
     Shape s;
+    s.ncodes = ncodes;
     bool all6 = true, in68 = true;
     for (int c = 0; c < ncodes; ++c) {
         const DevCode &D = codes[c]->dc;
+        s.nchunks = std::max(s.nchunks, D.nchunks);
         s.waves = std::max(s.waves, D.waves);
         s.cpt = std::max(s.cpt, D.cpt);
         s.nmax = std::max(s.nmax, D.n);
@@ -278,11 +281,62 @@ Shape shape_of(const lpdec_code *const *codes, int ncodes) {
 constexpr size_t kStaticLds = 1024;  // s_red + s_frame + alignment
 constexpr size_t kLdsLimit = 160 * 1024;
 
+// Two frames per workgroup (k_decode_pair): the code's plan of W waves (wave v
+// owns chunks v and v + W) becomes W virtual waves per frame, placed on 12
+// physical waves with at most one virtual wave of each frame per physical wave.
+// Wave p runs on SIMD p % 4 of its CU (waves are dealt to the SIMDs in turn), and
+// the check phase lasts as long as the SIMD with the most chunks, so the virtual
+// waves are placed largest first, each where its SIMD holds the fewest chunks so
+// far (then the physical wave with the fewest, then the lowest index).  Returns
+// the chunks of the busiest SIMD, or 0 if the plan does not fit.
+int pair_plan(int nchunks, int W, unsigned long long host[2]) {
+    constexpr int P = 12;
+    if (W < 1 || W > P || nchunks > 2 * W) return 0;
+    struct Item {
+        int size, slot, v;
+    };
+    std::vector<Item> items;
+    for (int slot = 0; slot < 2; ++slot)
+        for (int v = 0; v < W; ++v) items.push_back({(v < nchunks) + (v + W < nchunks), slot, v});
+    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.size > b.size; });
+    int hosted[P][2], load[P] = {0}, simd[4] = {0};
+    for (int p = 0; p < P; ++p) hosted[p][0] = hosted[p][1] = -1;
+    for (const Item &it : items) {
+        int best = -1;
+        for (int p = 0; p < P; ++p) {
+            if (hosted[p][it.slot] >= 0) continue;
+            if (best < 0 || simd[p % 4] < simd[best % 4] ||
+                (simd[p % 4] == simd[best % 4] && load[p] < load[best]))
+                best = p;
+        }
+        if (best < 0) return 0;
+        hosted[best][it.slot] = it.v;
+        load[best] += it.size;
+        simd[best % 4] += it.size;
+    }
+    host[0] = host[1] = 0;
+    for (int p = 0; p < P; ++p)
+        for (int slot = 0; slot < 2; ++slot)
+            host[slot] |= (unsigned long long)(hosted[p][slot] < 0 ? 0xF : hosted[p][slot]) << (4 * p);
+    return *std::max_element(simd, simd + 4);
+}
+
+// Chunks of the busiest SIMD for one frame of a code planned with W waves of
+// two chunks (wave v on SIMD v % 4).
+int single_busiest(int nchunks, int W) {
+    int simd[4] = {0};
+    for (int v = 0; v < W; ++v) simd[v % 4] += (v < nchunks) + (v + W < nchunks);
+    return *std::max_element(simd, simd + 4);
+}
+
 // Resident form: z,u in registers, slots and x in LDS.  Degree-6 codes: cpt <= 2
 // chunks per wave with their metadata, gamma/mu of <= 8 variables per thread,
-// <= 768 threads.  Check degrees 6..8: cpt <= 8 chunks per wave, metadata and
-// variable tables read from memory.
-bool resident_config(const Shape &s, LaunchConfig *cfg) {
+// <= 768 threads; one code whose variables all have degree 3 may run two frames
+// per workgroup (variant 1; the default when it evens out the SIMDs' chunks).
+// Check degrees 6..8: cpt <= 8 chunks per wave, metadata and variable tables
+// read from memory.
+bool resident_config(const Shape &s, LaunchConfig *cfg, int variant = -1) {
+    cfg->pair = false;
     if (s.dclass == 2) {
         // threads per template: cpt 1-2 up to 1024, cpt 4 up to 768, cpt 8 up to 512
         const int max_waves = s.cpt <= 2 ? kMaxWaves : (s.cpt <= 4 ? 12 : 8);
@@ -323,6 +377,22 @@ bool resident_config(const Shape &s, LaunchConfig *cfg) {
     cfg->lds_E = s.Emax;
     cfg->slot_stride = 0;
     cfg->state_stride = 0;
+    // two frames per workgroup: one code, two chunks per wave, variables of degree 3,
+    // <= 4 variables per thread of 12 waves; LDS holds each frame's slots and x
+    unsigned long long host[2];
+    const size_t pair_lds = 2 * lds;
+    const bool pair_ok = variant != 0 && s.ncodes == 1 && s.cpt == 2 && s.dv == 3 && s.nmax <= 4 * 12 * kWave &&
+                         pair_lds + kStaticLds <= kLdsLimit;
+    const int busiest = pair_ok ? pair_plan(s.nchunks, s.waves, host) : 0;
+    if (busiest > 0 && (variant >= 1 || busiest < 2 * single_busiest(s.nchunks, s.waves))) {
+        cfg->pair = true;
+        cfg->pair_host[0] = host[0];
+        cfg->pair_host[1] = host[1];
+        cfg->cpt_tmpl = 2;
+        cfg->vpt_tmpl = 4;
+        cfg->threads = 12 * kWave;
+        cfg->lds_bytes = pair_lds;
+    }
     return true;
 }
 
@@ -406,7 +476,8 @@ int blocks_per_cu(const LaunchConfig &cfg, const lpdec_code *code) {
 int occupancy_grid(const LaunchConfig &cfg, int frames, const lpdec_code *code) {
     DeviceInfo di = device_info();
     const int cus = di.cus > 0 ? di.cus : 256;
-    return std::max(1, std::min(frames, cus * blocks_per_cu(cfg, code)));
+    const int per_group = cfg.pair ? 2 : 1;  // frames a workgroup decodes at once
+    return std::max(1, std::min((frames + per_group - 1) / per_group, cus * blocks_per_cu(cfg, code)));
 }
 
 lpdec_status check_params(const lpdec_params *p);
@@ -420,7 +491,8 @@ lpdec_status resolve_config(const Shape &s, const lpdec_params &p, bool scattere
     if (half && mode != LPDEC_MODE_STREAMED && mode != LPDEC_MODE_AUTO)
         return fail(LPDEC_EUNSUPPORTED, "FP16 storage applies to the streamed form only");
     if (mode == LPDEC_MODE_AUTO) mode = half ? LPDEC_MODE_STREAMED : LPDEC_MODE_RESIDENT;
-    if (mode == LPDEC_MODE_RESIDENT && !resident_config(s, cfg)) {
+    if (mode == LPDEC_MODE_RESIDENT &&
+        !resident_config(s, cfg, code ? code->tune_variant[static_cast<int>(Form::Resident)] : -1)) {
         if (p.mode == LPDEC_MODE_RESIDENT)
             return fail(LPDEC_EUNSUPPORTED, "the register-resident form does not fit this code");
         mode = LPDEC_MODE_PERSISTENT_GLOBAL;
@@ -483,6 +555,13 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
     const bool half = p.storage == LPDEC_STORAGE_FP16;
     st = resolve_config(s, p, ncodes > 1 || code_of_frame || llr_off || done, &cfg, codes[0]);
     if (st != LPDEC_OK) return st;
+    // two frames per workgroup raise throughput only when every CU has two frames to
+    // run; with fewer frames they would leave CUs idle and double each frame's time,
+    // so the default keeps one frame per workgroup (an explicit variant 1 still pairs)
+    if (cfg.pair && codes[0]->tune_variant[static_cast<int>(Form::Resident)] < 1) {
+        const DeviceInfo di = device_info();
+        if (nframes < 2 * (di.cus > 0 ? di.cus : 256)) resident_config(s, &cfg, 0);
+    }
 
     Workspace &ws = ws_in ? *ws_in : c0->ws;
     WsGuard guard(ws, stream);
@@ -752,7 +831,10 @@ lpdec_status lpdec_code_launch_info(const lpdec_code *code, const lpdec_params *
     out->runtime_blocks_per_cu = q.occupancy;
     out->resource_blocks_per_cu = resource_blocks_per_cu(cfg, q);
     out->blocks_per_cu = blocks_per_cu(cfg, code);
-    out->variant = cfg.form != Form::Streamed ? -1 : (cfg.cpt_tmpl == 0 ? 0 : (cfg.staged ? 2 : 1));
+    if (cfg.form == Form::Streamed) out->variant = cfg.cpt_tmpl == 0 ? 0 : (cfg.staged ? 2 : 1);
+    else if (cfg.form == Form::Resident && cfg.dclass == 0 && cfg.dv == 3 && cfg.cpt_tmpl == 2)
+        out->variant = cfg.pair ? 1 : 0;
+    else out->variant = -1;
     return LPDEC_OK;
 }
 
@@ -780,7 +862,13 @@ lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, c
     st = resolve_config(shape_of(&one, 1), p, false, &cfg, nullptr);
     if (st != LPDEC_OK) return st;
     const int f = static_cast<int>(cfg.form);
-    const int nvar = cfg.form == Form::Streamed ? 3 : 1;
+    // resident: one or two frames per workgroup, where the code allows both
+    bool res_pair = false;
+    if (cfg.form == Form::Resident) {
+        LaunchConfig probe{};
+        res_pair = resident_config(shape_of(&one, 1), &probe, 1) && probe.pair;
+    }
+    const int nvar = cfg.form == Form::Streamed ? 3 : (res_pair ? 2 : 1);
     hipStream_t stream = static_cast<hipStream_t>(stream_v);
     const size_t n = (size_t)code->dc.n;
     float *x = nullptr;
@@ -801,7 +889,7 @@ lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, c
         for (int v = 0; v < nvar; ++v) {
             const int var = nvar == 1 ? -1 : v;
             code->tune_variant[f] = var;
-            if (nvar > 1) {  // a streamed variant the code does not allow falls back: skip it
+            if (cfg.form == Form::Streamed) {  // a streamed variant the code does not allow falls back: skip it
                 LaunchConfig probe{};
                 streamed_config(shape_of(&one, 1), p.storage == LPDEC_STORAGE_FP16, &probe, var);
                 const int got = probe.cpt_tmpl == 0 ? 0 : (probe.staged ? 2 : 1);

@@ -129,6 +129,10 @@ struct LaunchConfig {
     int lds_E;         // LDS slot array length (x follows it) when slots are in LDS
     int slot_stride;   // per-workgroup stride of global slot scratch (floats)
     int state_stride;  // per-workgroup stride of global state scratch (persistent-global form)
+    // resident form, two frames per workgroup (12 waves): for each slot, the virtual
+    // wave (the code plan's wave) that physical wave p hosts, in bits 4p..4p+3 (0xF: none)
+    bool pair;
+    unsigned long long pair_host[2];
 };
 
 hipError_t launch_decode(const LaunchConfig &cfg, const DevCode *codes_dev, const FrameBatch &fb,

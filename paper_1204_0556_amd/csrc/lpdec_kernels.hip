@@ -1059,6 +1059,340 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two frames per workgroup: the register-resident form for codes whose checks
+// all have degree 6 and whose variables all have degree 3, planned with two
+// chunks per wave.
+//
+// A CU deals the waves of a workgroup to its 4 SIMDs in turn, so waves w, w+4,
+// w+8 share a SIMD, and the check phase of an iteration lasts as long as the
+// SIMD that holds the most chunks: one frame of 21 chunks on 11 waves gives its
+// SIMDs 6, 6, 5 and 4.  Here a workgroup of 12 waves holds two frames
+// ("slots").  The code's plan of W waves (wave v owns chunks v and v + W) is kept
+// as W virtual waves per slot; each physical wave hosts at most one virtual wave
+// of each slot, in an assignment made on the host to even out the chunks per
+// SIMD (21 chunks: 11, 11, 10, 10 for two frames instead of 12).  A virtual wave
+// forms its residual sums exactly as a wave of the one-frame kernel does, and
+// the stopping test adds them in virtual-wave order, so results are bitwise the
+// same.
+//
+// The iteration loop runs both slots in step (x-updates, barrier, check updates,
+// barrier, two stopping tests).  Only when a frame stops does the workgroup
+// leave it: it writes that frame's x, flags and state, takes the next frame
+// from the queue, sets it up and rejoins the loop, while the other slot waits.
+// Once the queue is empty the remaining frame finishes in a one-slot loop.
+// ---------------------------------------------------------------------------
+constexpr int kPairWaves = 12;
+constexpr int kPairNone = 0xF;  // no virtual wave (4-bit field of the assignment)
+
+template <int VPT>
+__global__ void __launch_bounds__(kPairWaves * kWave, 1)
+k_decode_pair(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateIO sio,
+              unsigned long long host0, unsigned long long host1, int lds_E) {
+    constexpr int D = 6, DV = 3, NT = kPairWaves * kWave;
+    constexpr float inv = 1.0f / (float)DV;
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    __shared__ float s_red[2][2][kMaxWaves];
+    __shared__ int s_frame[2];
+    __shared__ int s_vote[2][kPairWaves];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const DevCode &C = codes[0];
+    const int W = C.waves;
+    const int region = lds_E + C.n;  // per slot: slots [lds_E], then x [n]
+    const float thr = ip.tol2 * (float)C.E;
+    const bool lw = lane < W;
+
+    // virtual wave of each slot hosted by this wave (-1: none); chunk k of this
+    // wave is chunk vw[k >> 1] + (k & 1) W of the code
+    int vw[2];
+    {
+        const int a = (int)((host0 >> (4 * wave)) & 0xFull), b = (int)((host1 >> (4 * wave)) & 0xFull);
+        vw[0] = a == kPairNone ? -1 : a;
+        vw[1] = b == kPairNone ? -1 : b;
+    }
+    float z[4][D], u[4][D];
+    uint32_t meta[4][D];
+    int coff[4];
+    int cpres = 0;  // bit k: chunk k exists (wave-uniform)
+    bool cval[4];   // this lane's check of chunk k exists
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int v = vw[k >> 1];
+        const int c = v + (k & 1) * W;
+        const bool has = v >= 0 && c < C.nchunks;
+        const ChunkDesc h = has ? chunk_desc(C, c) : ChunkDesc{0, 0, 0};
+        if (has) cpres |= 1 << k;
+        coff[k] = h.off;
+        cval[k] = lane < h.cnt;
+#pragma unroll
+        for (int e = 0; e < D; ++e) meta[k][e] = cval[k] ? C.edge_meta[h.off + e * kWave + lane] : 0u;
+    }
+    float vg[2][VPT];
+
+    // -- the iteration's phases for slot s --------------------------------------
+    auto phase_b = [&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        const float *slots = lds + s * region;
+        float *xs = lds + s * region + lds_E;
+#pragma unroll
+        for (int t = 0; t < VPT; ++t) {
+            const int i = tid + t * NT;
+            if (i < C.n) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int p = 0; p < DV; ++p) acc += slots[DV * i + p];
+                xs[i] = clamp01((acc - vg[s][t]) * inv);
+            }
+        }
+    };
+    auto phase_c = [&](auto sc) {  // check updates, the next iteration's slot writes, residuals
+        constexpr int s = decltype(sc)::value;
+        float *slots = lds + s * region;
+        const float *xs = lds + s * region + lds_E;
+        float rp = 0.0f, rd = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int k = 2 * s + j;
+            if (!(cpres & (1 << k))) continue;  // wave-uniform
+            if (cval[k]) {
+                check_update<D>(z[k], u[k], meta[k], xs, ip.rho, rp, rd);
+#pragma unroll
+                for (int e = 0; e < D; ++e) slots[meta[k][e] >> 16] = z[k][e] - u[k][e];
+            }
+        }
+        if (vw[s] >= 0) {
+            rp = wave_sum(rp);
+            rd = wave_sum(rd);
+            if (lane == 0) {
+                s_red[s][0][vw[s]] = rp;
+                s_red[s][1][vw[s]] = rd;
+            }
+        }
+    };
+    auto converged = [&](int s) -> bool {  // identical result in every wave
+        const float a = lw ? s_red[s][0][lane] : 0.0f;
+        const float b = lw ? s_red[s][1][lane] : 0.0f;
+        return __builtin_amdgcn_readfirstlane(wave_sum(a) < thr && wave_sum(b) < thr);
+    };
+
+    // -- frame changes ---------------------------------------------------------
+    // The next valid frame for slot s (>= nframes: the queue is empty).  With
+    // `fetched`, thread 0 took its queue position into s_frame[s] before the last
+    // barrier (when the previous frame stopped, so that the queue's latency hides
+    // behind writing that frame's x).  Frames with a non-finite LLR are completed
+    // on the way (x = 1/2, flags 0x80) and replaced from the queue.
+    auto frame_at = [&](int q) { return (fb.order && q < fb.nframes) ? fb.order[q] : q; };
+    auto acquire = [&](int s, bool fetched) -> int {
+        for (;;) {
+            if (!fetched) {
+                if (tid == 0) s_frame[s] = frame_at(atomicAdd(fb.queue, 1));
+                __syncthreads();
+            }
+            fetched = false;
+            const int f = __builtin_amdgcn_readfirstlane(s_frame[s]);
+            if (f >= fb.nframes || !frame_invalid(fb, f)) return f;
+            for (int i = tid; i < C.n; i += NT) fb.x_out[(fb.x_off ? fb.x_off[f] : (int64_t)f * C.n) + i] = 0.5f;
+            __syncthreads();  // also: every wave has read s_frame[s] before the next fetch
+            if (tid == 0) {
+                fb.iters_out[f] = 0;
+                fb.flags_out[f] = 0x80;
+                if (fb.done) {
+                    __threadfence_system();
+                    __hip_atomic_store(fb.done + f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                }
+            }
+        }
+    };
+    // gamma/mu and the state of frame f, then its slot writes (phase A)
+    auto setup = [&](auto sc, int f) {
+        constexpr int s = decltype(sc)::value;
+        float *slots = lds + s * region;
+        const float *gam = fb.llr + (fb.llr_off ? fb.llr_off[f] : (int64_t)f * C.n);
+#pragma unroll
+        for (int t = 0; t < VPT; ++t) {
+            const int i = tid + t * NT;
+            float g = 0.0f;
+            if (i < C.n) g = gam[C.var_identity ? i : C.var_orig[i]];
+            vg[s][t] = g * ip.mu_inv;
+        }
+        const size_t sbase = (size_t)f * C.E;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int k = 2 * s + j;
+#pragma unroll
+            for (int e = 0; e < D; ++e) {
+                float z0 = 0.0f, u0 = 0.0f;
+                if (sio.z_in && cval[k]) {
+                    const int ce = C.edge_csr[coff[k] + e * kWave + lane];
+                    z0 = sio.z_in[sbase + ce];
+                    u0 = sio.u_in[sbase + ce];
+                }
+                z[k][e] = z0;
+                u[k][e] = u0;
+            }
+            if (cval[k]) {
+#pragma unroll
+                for (int e = 0; e < D; ++e) slots[meta[k][e] >> 16] = z[k][e] - u[k][e];
+            }
+        }
+    };
+    // x, the parity votes and the state of the finished frame f
+    auto finish_x = [&](auto sc, int f) {
+        constexpr int s = decltype(sc)::value;
+        const float *xs = lds + s * region + lds_E;
+        const int64_t xoff = fb.x_off ? fb.x_off[f] : (int64_t)f * C.n;
+        float frac = 0.0f;
+        for (int i = tid; i < C.n; i += NT) {
+            const float x = xs[i];
+            fb.x_out[xoff + (C.var_identity ? i : C.var_orig[i])] = x;
+            frac = fmaxf(frac, fminf(x, 1.0f - x));
+        }
+        // parity of this wave's checks of slot s (the virtual waves cover every chunk once)
+        bool odd = false;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int k = 2 * s + j;
+            if (cval[k]) {
+                bool par = false;
+#pragma unroll
+                for (int e = 0; e < D; ++e) par ^= (xs[meta[k][e] & 0xffffu] >= 0.5f);
+                odd |= par;
+            }
+        }
+        const bool nonint = (double)frac > 1e-3;
+        const int vote = (__ballot(odd) ? 1 : 0) | (__ballot(nonint) ? 2 : 0);
+        if (lane == 0) s_vote[s][wave] = vote;
+        if (sio.z_out) {
+            const size_t sbase = (size_t)f * C.E;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int k = 2 * s + j;
+                if (cval[k]) {
+#pragma unroll
+                    for (int e = 0; e < D; ++e) {
+                        const int ce = C.edge_csr[coff[k] + e * kWave + lane];
+                        sio.z_out[sbase + ce] = z[k][e];
+                        sio.u_out[sbase + ce] = u[k][e];
+                    }
+                }
+            }
+        }
+    };
+    // Barrier between finish_x and finish_flags: the votes go through LDS; with
+    // host-visible completion flags the x and state stores must also have landed
+    // before a flag is raised, which a full barrier waits for.
+    auto flags_barrier = [&]() {
+        if (fb.done) __syncthreads();
+        else wg_barrier<true>();
+    };
+    // its iteration count and flags, after flags_barrier
+    auto finish_flags = [&](int s, int f, int iters, bool conv) {
+        if (tid == 0) {
+            int any_odd = 0, any_nonint = 0;
+            for (int w = 0; w < kPairWaves; ++w) {
+                any_odd |= s_vote[s][w] & 1;
+                any_nonint |= s_vote[s][w] & 2;
+            }
+            uint8_t fl = conv ? 0x01 : 0x00;
+            if (!any_nonint) fl |= 0x02;
+            if (!any_odd) fl |= 0x04;
+            if ((fl & 0x07) == 0x07) fl |= 0x08;
+            fb.iters_out[f] = iters;
+            fb.flags_out[f] = fl;
+            if (fb.done) {
+                __threadfence_system();
+                __hip_atomic_store(fb.done + f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+    };
+
+    constexpr std::integral_constant<int, 0> S0{};
+    constexpr std::integral_constant<int, 1> S1{};
+    int f0 = acquire(0, false), f1 = acquire(1, false);
+    bool live0 = f0 < fb.nframes, live1 = f1 < fb.nframes;
+    if (live0) setup(S0, f0);
+    if (live1) setup(S1, f1);
+    wg_barrier<true>();
+    int it0 = 1, it1 = 1;
+    if (live0 && live1) {
+        for (;;) {
+            phase_b(S0);
+            phase_b(S1);
+            wg_barrier<true>();
+            phase_c(S0);
+            __builtin_amdgcn_sched_barrier(0);  // the two slots' updates one after the other
+            phase_c(S1);
+            wg_barrier<true>();
+            const bool c0 = converged(0), c1 = converged(1);
+            const bool stop0 = c0 || it0 >= ip.max_iter, stop1 = c1 || it1 >= ip.max_iter;
+            if (!stop0 && !stop1) {
+                ++it0;
+                ++it1;
+                continue;
+            }
+            // a frame has stopped: fetch the next one's index, finish it, start the next one
+            if (tid == 0) {
+                if (stop0) s_frame[0] = frame_at(atomicAdd(fb.queue, 1));
+                if (stop1) s_frame[1] = frame_at(atomicAdd(fb.queue, 1));
+            }
+            if (stop0) finish_x(S0, f0);
+            if (stop1) finish_x(S1, f1);
+            flags_barrier();
+            if (stop0) finish_flags(0, f0, c0 ? it0 : ip.max_iter, c0);
+            if (stop1) finish_flags(1, f1, c1 ? it1 : ip.max_iter, c1);
+            if (!stop0) ++it0;
+            if (!stop1) ++it1;
+            if (stop0) {
+                f0 = acquire(0, true);
+                live0 = f0 < fb.nframes;
+                if (live0) {
+                    setup(S0, f0);
+                    it0 = 1;
+                }
+            }
+            if (stop1) {
+                f1 = acquire(1, true);
+                live1 = f1 < fb.nframes;
+                if (live1) {
+                    setup(S1, f1);
+                    it1 = 1;
+                }
+            }
+            wg_barrier<true>();  // the new frames' slot writes precede the x-update
+            if (!live0 || !live1) break;
+        }
+    }
+    // the queue is empty: the remaining frame (if any) finishes alone
+    auto tail = [&](auto sc, int f, int it) {
+        constexpr int s = decltype(sc)::value;
+        for (;;) {
+            phase_b(sc);
+            wg_barrier<true>();
+            phase_c(sc);
+            wg_barrier<true>();
+            const bool c = converged(s);
+            if (!(c || it >= ip.max_iter)) {
+                ++it;
+                continue;
+            }
+            if (tid == 0) s_frame[s] = frame_at(atomicAdd(fb.queue, 1));
+            finish_x(sc, f);
+            flags_barrier();
+            finish_flags(s, f, c ? it : ip.max_iter, c);
+            f = acquire(s, true);
+            if (f >= fb.nframes) break;
+            setup(sc, f);
+            it = 1;
+            wg_barrier<true>();
+        }
+    };
+    if (live0) tail(S0, f0, it0);
+    else if (live1) tail(S1, f1, it1);
+}
+
 // Streamed form set-up: zero (or load) each frame's state, flag invalid frames.
 template <bool HALF>
 __global__ void __launch_bounds__(256)
@@ -1205,8 +1539,32 @@ static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const 
     return hipErrorInvalidValue;
 }
 
+// two frames per workgroup (resident form, see k_decode_pair)
+static hipError_t go_pair(const LaunchConfig &cfg, const DevCode *codes, const FrameBatch &fb, const IterParams &ip,
+                          const StateIO &sio, hipStream_t stream, KernelQuery *q) {
+    if (cfg.threads != kPairWaves * kWave || cfg.vpt_tmpl != 4) return hipErrorInvalidConfiguration;
+    auto kern = k_decode_pair<4>;
+    if (cfg.lds_bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg.lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    if (q) {
+        hipFuncAttributes fa{};
+        hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kern));
+        if (e != hipSuccess) return e;
+        q->vgprs = fa.numRegs;
+        q->static_lds = (int)fa.sharedSizeBytes;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&q->occupancy, kern, cfg.threads, cfg.lds_bytes);
+    }
+    hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(cfg.threads), cfg.lds_bytes, stream, codes, fb, ip, sio,
+                       cfg.pair_host[0], cfg.pair_host[1], cfg.lds_E);
+    return hipGetLastError();
+}
+
 hipError_t launch_decode(const LaunchConfig &cfg, const DevCode *codes_dev, const FrameBatch &fb,
                          const IterParams &ip, const StateIO &sio, const StreamArgs &sa, hipStream_t stream) {
+    if (cfg.pair) return go_pair(cfg, codes_dev, fb, ip, sio, stream, nullptr);
     if (cfg.dclass == 0) return go_range<6, 6>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
     if (cfg.dclass == 2) return go_range<6, 8>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
     return go_range<2, 8>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
@@ -1218,6 +1576,7 @@ hipError_t decode_query(const LaunchConfig &cfg, KernelQuery *q) {
     StateIO sio{};
     StreamArgs sa{};
     *q = KernelQuery{};
+    if (cfg.pair) return go_pair(cfg, nullptr, fb, ip, sio, nullptr, q);
     if (cfg.dclass == 0) return go_range<6, 6>(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
     if (cfg.dclass == 2) return go_range<6, 8>(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
     return go_range<2, 8>(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
