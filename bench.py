@@ -476,7 +476,8 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=6144,
                     help="oracle sample size (frames; about 10-15 s of host time)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the plain and streamed comparisons")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the plain and streamed comparisons and the per-Eb/N0 blocks decoded alone")
     ap.add_argument("--workload", default="headline",
                     choices=["headline", "uneven", "precision", "serving", "bsc", "sweep", "dual"])
     ap.add_argument("--bsc-frames", type=int, default=128, help="frames per code and crossover (bsc workload)")
@@ -577,17 +578,18 @@ def main():
     for b, s in enumerate(W.HEADLINE_SNRS):
         sl = slice(b * FRAMES_PER_SNR, (b + 1) * FRAMES_PER_SNR)
         errs = int(np.sum((x[sl] >= 0.5).any(axis=1)))
-        # the block decoded alone (same form), for per-SNR throughput
-        blk = llr[sl].contiguous()
-        (_, bit, _), bms = _timed(torch, lambda: lp.decode(code, blk, mode=mode, **P), steps=2, warmup=1)
-        bfi = int(bit.cpu().numpy().astype(np.int64).sum())
         fer[str(s)] = {"frame_errors": errs, "fer": errs / FRAMES_PER_SNR,
                        "fer_ci95": _clopper_pearson(errs, FRAMES_PER_SNR),
                        "ml_lower_bound_errors": int(((ml_oc[sl] & lp.EVAL_ML_ERROR) != 0).sum()),
-                       "mean_iters": float(iters[sl].mean()),
-                       "alone_mbit_s": round(FRAMES_PER_SNR * H.n / (bms / 1e3) / 1e6, 1),
-                       "alone_info_mbit_s": round(FRAMES_PER_SNR * k_info / (bms / 1e3) / 1e6, 1),
-                       "alone_hbm_equivalent_gbs": round(B * bfi / (bms / 1e3) / 1e9, 1)}
+                       "mean_iters": float(iters[sl].mean())}
+        if not args.no_extra:
+            # the block decoded alone (same form), for per-SNR throughput
+            blk = llr[sl].contiguous()
+            (_, bit, _), bms = _timed(torch, lambda: lp.decode(code, blk, mode=mode, **P), steps=2, warmup=1)
+            bfi = int(bit.cpu().numpy().astype(np.int64).sum())
+            fer[str(s)].update({"alone_mbit_s": round(FRAMES_PER_SNR * H.n / (bms / 1e3) / 1e6, 1),
+                                "alone_info_mbit_s": round(FRAMES_PER_SNR * k_info / (bms / 1e3) / 1e6, 1),
+                                "alone_hbm_equivalent_gbs": round(B * bfi / (bms / 1e3) / 1e9, 1)})
 
     res = {
         "metric": METRIC,
