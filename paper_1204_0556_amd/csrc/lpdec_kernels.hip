@@ -1333,10 +1333,17 @@ k_decode_pair(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, S
                 ++it1;
                 continue;
             }
-            // a frame has stopped: fetch the next one's index, finish it, start the next one
+            // a frame has stopped: fetch the next one's index, finish it, start the next
+            // one.  Near the end of the queue (fewer frames left than workgroups) a slot
+            // whose partner keeps running takes no new frame: the workgroup then runs one
+            // frame at a time, each at the one-frame rate, so that the last frames do not
+            // run at the shared rate while other CUs have nothing left.  The partner's
+            // one-slot loop keeps taking frames, so none is left behind.
             if (tid == 0) {
-                if (stop0) s_frame[0] = frame_at(atomicAdd(fb.queue, 1));
-                if (stop1) s_frame[1] = frame_at(atomicAdd(fb.queue, 1));
+                const bool late = __hip_atomic_load(fb.queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                                  fb.nframes - (int)gridDim.x;
+                if (stop0) s_frame[0] = (late && !stop1) ? fb.nframes : frame_at(atomicAdd(fb.queue, 1));
+                if (stop1) s_frame[1] = late ? fb.nframes : frame_at(atomicAdd(fb.queue, 1));
             }
             if (stop0) finish_x(S0, f0);
             if (stop1) finish_x(S1, f1);
