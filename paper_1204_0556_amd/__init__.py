@@ -83,6 +83,10 @@ def _load():
     if not os.path.exists(library_path):
         raise ImportError(f"{library_path} is missing: build it with paper_1204_0556_amd/build.py "
                           "(python -c 'import __graft_entry__; __graft_entry__.build()')")
+    # torch brings its own HIP runtime.  Loading it first makes the library bind to
+    # that same runtime, so tensors, streams and the library's launches share one;
+    # loaded the other way round, the process would hold two HIP runtimes.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(library_path)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     P = ctypes.POINTER
