@@ -245,9 +245,10 @@ lpdec_status lpdec_code_launch_info(const lpdec_code *code, const lpdec_params *
  *   variant        see lpdec_launch_info.variant.  Streamed form: 0, 1 or 2; a
  *                  variant the code does not allow falls back to the next lower
  *                  one; -1 restores the default (the highest allowed).  Resident
- *                  form: 0 or 1 (1 falls back to 0 where the code does not allow
- *                  two frames per workgroup, and is then used for every batch
- *                  size); -1 restores the default.  Ignored by the
+ *                  form: 0 one frame per workgroup; 1 two frames per workgroup for
+ *                  every batch size (0 where the code does not allow it); -1
+ *                  restores the default (two frames where they help, for batches
+ *                  of at least two frames per CU).  Ignored by the
  *                  persistent-global form.
  * Not synchronised with decodes running on other threads. */
 lpdec_status lpdec_code_set_tuning(lpdec_code *code, int32_t mode, int32_t blocks_per_cu,
