@@ -139,6 +139,33 @@ lpdec_status lpdec_decode_state(const lpdec_code *code, int32_t batch, const flo
                                 uint8_t *flags_out, float *z_state, float *u_state,
                                 int32_t state_flags, void *stream);
 
+/* lpdec_decode for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The call
+ * makes no device or host allocation of its own (no hipMalloc, hipFree,
+ * hipHostMalloc, event creation or workspace growth): its scratch -- the
+ * persistent launch's queue counter and the per-workgroup buffers of the
+ * persistent forms -- lives in one static device array of
+ * LPDEC_NOALLOC_SCRATCH_BYTES per GPU, loaded with the library and held until
+ * the process ends.  The caller still passes llr, x_out, iters_out and flags_out
+ * (device, as lpdec_decode).
+ *   - Forms: the persistent ones (mode AUTO, RESIDENT or PERSISTENT_GLOBAL, FP32
+ *     storage).  The streamed form and FP16 storage keep every frame's state in
+ *     HBM, which the array does not hold: LPDEC_EUNSUPPORTED.
+ *   - Size: when the persistent-global form needs per-workgroup buffers, the
+ *     grid is cut to what the array holds (results do not depend on the grid);
+ *     a code whose single workgroup needs more than the array is rejected with
+ *     LPDEC_EUNSUPPORTED (no code within this library's limits does).
+ *   - Results are bitwise those of lpdec_decode with the same parameters.
+ *   - Every call on one GPU shares that GPU's array, and the array keeps the last
+ *     call's contents (each call resets what must start at zero with a kernel,
+ *     not a memset).  Calls that overlap on one GPU -- on different streams, or
+ *     from different threads -- race on the array and give undefined results:
+ *     serialise them.  Asynchronous on `stream`, like lpdec_decode. */
+#define LPDEC_NOALLOC_SCRATCH_BYTES (64 * 1024 * 1024)
+lpdec_status lpdec_decode_noalloc(const lpdec_code *code, int32_t batch, const float *llr,
+                                  const lpdec_params *p, float *x_out, int32_t *iters_out,
+                                  uint8_t *flags_out, void *stream);
+
 /* Batched uneven decoding: `nframes` frames drawn from `ncodes` codes, decoded in
  * one persistent launch with per-frame early termination.
  *   codes          host [ncodes] code handles

@@ -17,7 +17,7 @@ import os
 import numpy as np
 
 __all__ = [
-    "Code", "decode", "decode_state", "decode_multi", "project", "default_params", "last_error",
+    "Code", "decode", "decode_noalloc", "decode_state", "decode_multi", "project", "default_params", "last_error",
     "LpdecError", "FLAG_CONVERGED", "FLAG_INTEGRAL", "FLAG_CODEWORD", "FLAG_CERTIFIED", "FLAG_INVALID",
     "MODE_AUTO", "MODE_RESIDENT", "MODE_STREAMED", "MODE_PERSISTENT_GLOBAL", "STORAGE_FP32", "STORAGE_FP16",
     "MAX_CHECK_DEGREE", "library_path", "Server", "EXECUTOR_GPU", "EXECUTOR_HOST_NULL",
@@ -100,6 +100,8 @@ def _load():
     lib.lpdec_code_get_info.restype = ctypes.c_int
     lib.lpdec_decode.argtypes = [vp, i32, vp, P(_Params), vp, vp, vp, vp]
     lib.lpdec_decode.restype = ctypes.c_int
+    lib.lpdec_decode_noalloc.argtypes = [vp, i32, vp, P(_Params), vp, vp, vp, vp]
+    lib.lpdec_decode_noalloc.restype = ctypes.c_int
     lib.lpdec_decode_state.argtypes = [vp, i32, vp, P(_Params), vp, vp, vp, vp, vp, i32, vp]
     lib.lpdec_decode_state.restype = ctypes.c_int
     lib.lpdec_decode_multi.argtypes = [P(vp), i32, i32, P(i32), P(i64), vp, i64, P(_Params), vp, P(i64), i64,
@@ -276,6 +278,23 @@ def decode(code: Code, llr, out=None, stream=None, **params):
     _check(_lib.lpdec_decode(code.handle, B, _dev_ptr(llr, torch.float32, "llr"), ctypes.byref(p),
                              _dev_ptr(x, torch.float32, "x"), _dev_ptr(it, torch.int32, "iters"),
                              _dev_ptr(fl, torch.uint8, "flags"), _stream(stream)))
+    return x, it, fl
+
+
+def decode_noalloc(code: Code, llr, out, stream=None, **params):
+    """decode() through lpdec_decode_noalloc: the library allocates nothing (its
+    scratch is a static device array per GPU); the caller supplies the outputs
+    out = (x [B,n] f32, iters [B] i32, flags [B] u8).  Calls that overlap on one
+    GPU race on that array.  Persistent forms only (FP32 storage)."""
+    torch = _torch()
+    B = int(llr.shape[0]) if llr.dim() == 2 else 1
+    if llr.numel() != B * code.n:
+        raise ValueError("llr must be [batch, n]")
+    x, it, fl = out
+    p = _params(**params)
+    _check(_lib.lpdec_decode_noalloc(code.handle, B, _dev_ptr(llr, torch.float32, "llr"), ctypes.byref(p),
+                                     _dev_ptr(x, torch.float32, "x"), _dev_ptr(it, torch.int32, "iters"),
+                                     _dev_ptr(fl, torch.uint8, "flags"), _stream(stream)))
     return x, it, fl
 
 

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblpdec.so")
-SOURCES = ["lpdec_kernels.hip", "lpdec_aux.hip", "lpdec_host.cpp", "lpdec_aux_host.cpp", "lpdec_server.cpp"]
+SOURCES = ["lpdec_kernels.hip", "lpdec_aux.hip", "lpdec_host.cpp", "lpdec_aux_host.cpp", "lpdec_server.cpp",
+           "lpdec_noalloc.hip"]
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no implicit FMA contraction: every fused multiply-add is an explicit fmaf,

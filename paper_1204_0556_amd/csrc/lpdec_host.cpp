@@ -530,7 +530,7 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
                                const int32_t *code_of_frame, const int64_t *llr_off, const int64_t *x_off,
                                const float *llr, const lpdec_params *pin, float *x_out, int32_t *iters_out,
                                uint8_t *flags_out, float *z_state, float *u_state, int state_flags, void *stream_v,
-                               Workspace *ws_in, int *done) {
+                               Workspace *ws_in, int *done, const ScratchArena *arena) {
     lpdec_params p = pin ? *pin : lpdec_default_params();
     lpdec_status st = check_params(&p);
     if (st != LPDEC_OK) return st;
@@ -555,6 +555,12 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
     const bool half = p.storage == LPDEC_STORAGE_FP16;
     st = resolve_config(s, p, ncodes > 1 || code_of_frame || llr_off || done, &cfg, codes[0]);
     if (st != LPDEC_OK) return st;
+    if (arena && (ncodes > 1 || code_of_frame || llr_off || done))
+        return fail(LPDEC_EINVAL, "lent scratch serves dense single-code batches only");
+    if (arena && cfg.form == Form::Streamed)
+        return fail(LPDEC_EUNSUPPORTED,
+                    "the allocation-free decode runs the persistent forms only (FP32 storage, mode AUTO, RESIDENT "
+                    "or PERSISTENT_GLOBAL): the streamed form keeps every frame's state in HBM");
     // two frames per workgroup raise throughput only when every CU has two frames to
     // run; with fewer frames they would leave CUs idle and double each frame's time,
     // so the default keeps one frame per workgroup (an explicit variant 1 still pairs)
@@ -564,7 +570,10 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
     }
 
     Workspace &ws = ws_in ? *ws_in : c0->ws;
-    WsGuard guard(ws, stream);
+    // with lent scratch the code's workspace is not used, so it is neither locked
+    // nor ordered after other calls (its event would be created on first use)
+    std::unique_ptr<WsGuard> guard;
+    if (!arena) guard.reset(new WsGuard(ws, stream));
 
     // per-launch code table and frame metadata
     const DevCode *codes_dev = c0->d_dc;
@@ -646,27 +655,75 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
 
     if (cfg.form == Form::Resident || cfg.form == Form::PersistentGlobal) {
         cfg.grid = occupancy_grid(cfg, nframes, codes[0]);
-        HIP_TRY(ws.queue.ensure(sizeof(int)));
-        fb.queue = static_cast<int *>(ws.queue.p);
-        HIP_TRY(launch_fill_i32(fb.queue, 0, 1, stream));
-        if (s.permuted && cfg.vpt_tmpl == 0) {  // gamma/mu staged in internal variable order
-            HIP_TRY(ws.gmu.ensure(sizeof(float) * (size_t)cfg.grid * s.nmax));
-            sa.gmu = static_cast<float *>(ws.gmu.p);
+        // per-workgroup scratch (bytes per workgroup of each buffer; 0: not used)
+        const bool need_gmu = s.permuted && cfg.vpt_tmpl == 0;  // gamma/mu staged in internal variable order
+        const bool pg = cfg.form == Form::PersistentGlobal;
+        const size_t b_gmu = need_gmu ? sizeof(float) * (size_t)s.nmax : 0;
+        const size_t b_state = pg ? 2 * sizeof(float) * (size_t)cfg.state_stride : 0;
+        const size_t b_xprev = (pg && cfg.slot_mode == 2) ? sizeof(unsigned) * (size_t)s.nmax : 0;
+        const size_t b_slots = (pg && cfg.slot_mode == 0) ? sizeof(float) * (size_t)cfg.slot_stride : 0;
+        void *p_queue, *p_gmu, *p_state, *p_xprev, *p_slots;
+        if (arena) {
+            // queue counter, then each buffer 256-byte aligned; the grid is cut so
+            // that all of them fit (a frame's result does not depend on the grid)
+            const size_t per_wg = b_gmu + b_state + b_xprev + b_slots, fixed = 256 + 4 * 255;
+            if (per_wg > 0) {
+                if (fixed + per_wg > arena->bytes)
+                    return fail(LPDEC_EUNSUPPORTED,
+                                "one workgroup of this code needs %zu bytes of scratch; the allocation-free decode "
+                                "holds %zu",
+                                fixed + per_wg, arena->bytes);
+                cfg.grid = (int)std::min<size_t>((size_t)cfg.grid, (arena->bytes - fixed) / per_wg);
+            }
+            auto align = [](size_t b) { return (b + 255) / 256 * 256; };
+            size_t off = 0;
+            auto carve = [&](size_t per) -> void * {
+                void *q = arena->base + off;
+                off += align(per * (size_t)cfg.grid);
+                return per ? q : nullptr;
+            };
+            p_queue = arena->base;
+            off = 256;
+            p_gmu = carve(b_gmu);
+            p_state = carve(b_state);
+            p_xprev = carve(b_xprev);
+            p_slots = carve(b_slots);
+            if (off > arena->bytes) return fail(LPDEC_EINVAL, "internal: scratch layout exceeds the arena");
+        } else {
+            HIP_TRY(ws.queue.ensure(sizeof(int)));
+            p_queue = ws.queue.p;
+            p_gmu = p_state = p_xprev = p_slots = nullptr;
+            if (b_gmu) {
+                HIP_TRY(ws.gmu.ensure(b_gmu * cfg.grid));
+                p_gmu = ws.gmu.p;
+            }
+            if (b_state) {
+                HIP_TRY(ws.gstate.ensure(b_state * cfg.grid));
+                p_state = ws.gstate.p;
+            }
+            if (b_xprev) {
+                HIP_TRY(ws.gxprev.ensure(b_xprev * cfg.grid));
+                p_xprev = ws.gxprev.p;
+            }
+            if (b_slots) {
+                HIP_TRY(ws.gslots.ensure(b_slots * cfg.grid));
+                p_slots = ws.gslots.p;
+            }
+        }
+        fb.queue = static_cast<int *>(p_queue);
+        HIP_TRY(launch_fill_i32(fb.queue, 0, 1, stream));  // a kernel, not a memset: safe under graph capture
+        if (need_gmu) {
+            sa.gmu = static_cast<float *>(p_gmu);
             sa.gmu_stride = s.nmax;
         }
-        if (cfg.form == Form::PersistentGlobal) {
-            HIP_TRY(ws.gstate.ensure(2 * sizeof(float) * (size_t)cfg.grid * cfg.state_stride));
-            sa.z = ws.gstate.p;
-            sa.u = static_cast<float *>(ws.gstate.p) + (size_t)cfg.grid * cfg.state_stride;
+        if (pg) {
+            sa.z = p_state;
+            sa.u = static_cast<float *>(p_state) + (size_t)cfg.grid * cfg.state_stride;
             if (cfg.slot_mode == 2) {
-                HIP_TRY(ws.gxprev.ensure(sizeof(unsigned) * (size_t)cfg.grid * s.nmax));
-                sa.gxprev = static_cast<unsigned *>(ws.gxprev.p);
+                sa.gxprev = static_cast<unsigned *>(p_xprev);
                 sa.gmu_stride = s.nmax;
             }
-            if (cfg.slot_mode == 0) {
-                HIP_TRY(ws.gslots.ensure(sizeof(float) * (size_t)cfg.grid * cfg.slot_stride));
-                sa.gslots = static_cast<float *>(ws.gslots.p);
-            }
+            if (cfg.slot_mode == 0) sa.gslots = static_cast<float *>(p_slots);
         }
         hipError_t e = launch_decode(cfg, codes_dev, fb, ip, sio, sa, stream);
         if (e != hipSuccess) return fail(LPDEC_EDEVICE, "decode launch failed: %s", hipGetErrorString(e));

@@ -96,9 +96,18 @@ struct lpdec_code {
 // Sets the thread-local message returned by lpdec_last_error() and returns st.
 lpdec_status lpdec_fail(lpdec_status st, const char *fmt, ...);
 
+// Device scratch lent by the caller of a decode that must not allocate: the
+// queue counter and every per-workgroup buffer of the persistent forms are carved
+// out of it, and the persistent grid is cut to what it holds (results do not
+// depend on the grid).  No workspace, event or lock of the code is touched.
+struct ScratchArena {
+    char *base;    // device address, 256-byte aligned
+    size_t bytes;  // capacity
+};
+
 // Decode core shared by every entry point (see lpdec_host.cpp).
 lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int nframes,
                                const int32_t *code_of_frame, const int64_t *llr_off, const int64_t *x_off,
                                const float *llr, const lpdec_params *pin, float *x_out, int32_t *iters_out,
                                uint8_t *flags_out, float *z_state, float *u_state, int state_flags, void *stream_v,
-                               Workspace *ws_in, int *done);
+                               Workspace *ws_in, int *done, const ScratchArena *arena = nullptr);

@@ -85,6 +85,9 @@ def test_null_arguments(lib):
     assert lib.lpdec_decode(None, 1, None, None, None, None, None, None) == EINVAL
     assert "code" in lib.lpdec_last_error().decode()
     lib.lpdec_code_destroy(None)  # NULL-safe
+    lib.lpdec_decode_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 6
+    assert lib.lpdec_decode_noalloc(None, 1, None, None, None, None, None, None) == EINVAL
+    assert "code" in lib.lpdec_last_error().decode()
 
 
 def test_project_argument_checks(lib):
