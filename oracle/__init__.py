@@ -110,6 +110,16 @@ def max_linear(c):
     return z
 
 
+def host_threads(cap: int = 16) -> int:
+    """Worker threads for batch decodes: the cores this process may run on (its CPU
+    affinity, which can be fewer than the machine has), at most `cap`."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, cap))
+
+
 class Result:
     def __init__(self, x, iters, flags, z=None, u=None, proj_counts=None):
         self.x, self.iters, self.flags, self.z, self.u, self.proj_counts = x, iters, flags, z, u, proj_counts
@@ -145,7 +155,7 @@ def decode(H, llr, mu=3.0, rho=1.9, max_iter=1000, tol=1e-5, state=False, z0=Non
         zp = up = None
     counts = np.zeros(3, np.int64)
     if nthreads is None:
-        nthreads = os.cpu_count() or 1
+        nthreads = host_threads()
     rc = lib.lpo_decode_batch(H.m, n, _ptr(rp, ctypes.c_int), _ptr(ci, ctypes.c_int), B,
                               _ptr(llr, ctypes.c_float), float(mu), float(rho), int(max_iter), float(tol),
                               _ptr(x, ctypes.c_double), _ptr(it, ctypes.c_int), _ptr(fl, ctypes.c_ubyte),

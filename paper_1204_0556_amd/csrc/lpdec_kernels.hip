@@ -322,19 +322,38 @@ __device__ __forceinline__ float x_update(const float *slots, const VarLoc &L, f
 }
 
 // Exact, order-independent per-variable sums for codes whose slot array does not
-// fit in LDS: each replica difference w is converted to signed 32.32 fixed point
-// (exact for 2^-9 <= |w| < 2^31; smaller magnitudes are rounded down to a multiple
-// of 2^-32; larger ones saturate) and accumulated with 64-bit integer LDS atomics.  Integer addition is
-// associative, so the sum does not depend on the order the lanes arrive in.
+// fit in LDS: each replica difference w is converted to signed 32.32 fixed point,
+// floor(w 2^32) (exact for 2^-9 <= |w| < 2^31; smaller magnitudes are rounded
+// toward -infinity to a multiple of 2^-32; |w| >= 2^31 saturates to the largest
+// value of its sign), and accumulated with 64-bit integer LDS atomics.  Integer
+// addition is associative, so the sum does not depend on the order the lanes
+// arrive in.  Both conversions use integer operations only: the float's
+// significand is shifted into place by its exponent.
 __device__ __forceinline__ unsigned long long to_fixed(float w) {
-    const double d = fmin(fmax((double)w, -2147483648.0), 2147483647.0);  // saturate to the range
-    const double hi = floor(d);
-    const double lo = (d - hi) * 4294967296.0;  // fraction, in [0, 2^32)
-    return ((unsigned long long)(unsigned)(int)hi << 32) | (unsigned long long)(unsigned)lo;
+    const unsigned b = __float_as_uint(w);
+    const int e = (int)((b >> 23) & 0xffu);  // biased exponent (0: zero or subnormal)
+    const unsigned long long m = (b & 0x7fffffu) | (e != 0 ? 0x800000u : 0u);
+    const int sh = max(e, 1) - 118;  // |w| 2^32 = m 2^sh  (2^(e-127-23+32))
+    unsigned long long mag;
+    bool cut;  // nonzero bits shifted out
+    if (sh >= 0) {
+        mag = m << min(sh, 39);
+        cut = false;
+    } else {
+        const int r = min(-sh, 63);
+        mag = m >> r;
+        cut = (m & ((1ull << r) - 1ull)) != 0ull;
+    }
+    const bool neg = (b >> 31) != 0u;
+    // floor: a negative value with bits cut off rounds away from zero
+    unsigned long long v = neg ? 0ull - (mag + (cut ? 1ull : 0ull)) : mag;
+    if (e >= 158) v = neg ? 0x8000000000000000ull : 0x7fffffff00000000ull;  // |w| >= 2^31
+    return v;
 }
+// The sum back to FP32: a correctly rounded conversion of the signed 64-bit value
+// (integer normalisation, no FP64), then an exact scale by 2^-32.
 __device__ __forceinline__ float from_fixed(unsigned long long a) {
-    const double d = (double)(int)(unsigned)(a >> 32) * 4294967296.0 + (double)(unsigned)a;
-    return (float)(d * (1.0 / 4294967296.0));
+    return (float)(long long)a * 0x1p-32f;
 }
 
 // one check update of degree D on registers z,u (length DMAX arrays); x is read
@@ -1010,7 +1029,8 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 odd |= par;
             }
         }
-        const bool nonint = (double)frac > 1e-3;
+        // frac > 1e-3 exactly: 1e-3f is the least float above 1e-3
+        const bool nonint = frac >= 1e-3f;
         const int any_odd = __syncthreads_or(odd);
         const int any_nonint = __syncthreads_or(nonint);
         if (tid == 0) {
@@ -1262,7 +1282,8 @@ k_decode_pair(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, S
                 odd |= par;
             }
         }
-        const bool nonint = (double)frac > 1e-3;
+        // frac > 1e-3 exactly: 1e-3f is the least float above 1e-3
+        const bool nonint = frac >= 1e-3f;
         const int vote = (__ballot(odd) ? 1 : 0) | (__ballot(nonint) ? 2 : 0);
         if (lane == 0) s_vote[s][wave] = vote;
         if (sio.z_out) {
