@@ -15,7 +15,14 @@
  *   - "device" pointers are HIP device allocations owned by the caller (e.g. torch
  *     tensors); they must stay valid until the work queued on `stream` completes.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Decode
- *     calls are asynchronous on it: outputs are ready when the stream is.
+ *     calls are asynchronous on it: outputs are ready when the stream is.  Two
+ *     exceptions block the calling thread: the streamed form (one launch per
+ *     iteration) queues its launches in blocks of 16, reads after each block how
+ *     many frames are still unfinished (so a decode that converges early stops
+ *     issuing launches) and returns only after its iterations have run; and a call
+ *     with scattered frames (lpdec_decode_multi) first waits for the previous such
+ *     call on the same code to finish, because it reuses that call's pinned staging
+ *     of the per-frame metadata.
  *   - Arguments are validated on the host before anything is queued; a rejected
  *     call queues no work.  Per-frame problems (non-finite LLRs) are reported in
  *     the frame's flags and never abort the batch.
@@ -308,10 +315,16 @@ lpdec_status lpdec_project(int32_t d, int32_t count, const float *v, float *z, v
  *
  * Requests (frames of one code) are submitted from host memory at any time.  A
  * dispatcher thread admits them in arrival order while their device footprint
- * (4 n bytes of LLRs per frame) fits the budget, stages their LLRs into HBM and
- * launches them on one of `max_inflight` streams, so requests that arrive while
- * others are decoding start as soon as a stream and memory are free and run
- * concurrently with them.  Each frame's completion is signalled by the kernel
+ * fits the budget, stages their LLRs into HBM and launches them on one of
+ * `max_inflight` streams, so requests that arrive while others are decoding start
+ * as soon as a stream and memory are free and run concurrently with them.
+ * budget_bytes bounds all device memory the server allocates: each launch slot
+ * owns a scratch region (queue counter, per-frame metadata and the persistent
+ * forms' per-workgroup state), sized at creation for a launch of max_batch_frames
+ * frames of the most demanding code at its full grid but to at most half the
+ * budget over all slots (a slot then runs fewer workgroups at once; results do
+ * not change), and the rest is the LLR arena, of which each admitted frame holds
+ * 4 n bytes until its request completes.  The dispatcher allocates nothing.  Each frame's completion is signalled by the kernel
  * itself, so a request completes when its own frames do, not when its launch
  * does.  Codes stay resident; a frame's result is the same alone or in the mix.
  * Latency = submit to host-visible result. */
@@ -335,15 +348,17 @@ lpdec_server_config lpdec_server_default_config(void);
 /* codes: host [ncodes] code handles (GPU executor), or NULL with code_n: host [ncodes]
  * code lengths (host-null executor only).  p: NULL = lpdec_default_params(); only the
  * resident and persistent-global forms (FP32) serve.  The server keeps pointers to the
- * codes: destroy the server before its codes.  Errors: LPDEC_EINVAL, LPDEC_ENOMEM,
- * LPDEC_EDEVICE, LPDEC_EUNSUPPORTED. */
+ * codes: destroy the server before its codes.  Errors: LPDEC_EINVAL (also a budget
+ * too small for the launch slots' scratch and one frame of the shortest code),
+ * LPDEC_ENOMEM, LPDEC_EDEVICE, LPDEC_EUNSUPPORTED. */
 lpdec_status lpdec_server_create(const lpdec_code *const *codes, const int32_t *code_n, int32_t ncodes,
                                  const lpdec_params *p, const lpdec_server_config *cfg,
                                  lpdec_server **out);
 
 /* Submit `frames` frames of code `code`; llr is host [frames*n] FP32, copied before
  * return.  *ticket identifies the request.  Errors: LPDEC_EINVAL (bad code or frame
- * count, or a request larger than the whole budget), LPDEC_EBUSY (max_pending queued). */
+ * count, or a request larger than the whole LLR arena), LPDEC_EBUSY (max_pending
+ * queued). */
 lpdec_status lpdec_server_submit(lpdec_server *s, int32_t code, int32_t frames, const float *llr,
                                  int64_t *ticket);
 
@@ -365,11 +380,14 @@ lpdec_status lpdec_server_cancel(lpdec_server *s, int64_t ticket);
 typedef struct {
     int64_t submitted, completed, cancelled, rejected;
     int64_t frames_completed, bits_completed; /* coded bits */
-    int64_t inflight_bytes, peak_bytes;        /* admitted device footprint: now, maximum */
+    int64_t inflight_bytes, peak_bytes;        /* LLR arena held by admitted frames: now, maximum */
     int64_t launches;
     int32_t queued, running;
     double p50_latency_s, p99_latency_s, mean_latency_s, max_latency_s;
-    double elapsed_s; /* first submit to last completion */
+    double elapsed_s;                          /* first submit to last completion */
+    int64_t workspace_bytes;                   /* launch slots' scratch (fixed at creation)      */
+    int64_t peak_device_bytes;                 /* workspace_bytes + peak_bytes (<= budget_bytes) */
+    int32_t peak_concurrent_launches;          /* launches in flight at once, at most            */
 } lpdec_server_stats;
 
 lpdec_status lpdec_server_get_stats(lpdec_server *s, lpdec_server_stats *st);

@@ -76,7 +76,8 @@ class _ServerStats(ctypes.Structure):
                 ("peak_bytes", ctypes.c_int64), ("launches", ctypes.c_int64), ("queued", ctypes.c_int32),
                 ("running", ctypes.c_int32), ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
                 ("mean_latency_s", ctypes.c_double), ("max_latency_s", ctypes.c_double),
-                ("elapsed_s", ctypes.c_double)]
+                ("elapsed_s", ctypes.c_double), ("workspace_bytes", ctypes.c_int64),
+                ("peak_device_bytes", ctypes.c_int64), ("peak_concurrent_launches", ctypes.c_int32)]
 
 
 def _load():

@@ -252,6 +252,7 @@ struct Shape {
     int ncodes = 0, nchunks = 0;
     int waves = 0, cpt = 0, nmax = 0, Emax = 0, Eint_max = 0, dclass = 0;
     int dv = 0;  // common variable degree of all codes (0 if mixed)
+    int dreg = 0;  // common check degree of all codes (0 if mixed)
     bool permuted = false;  // some code renumbers its variables
 };
 
@@ -275,6 +276,9 @@ Shape shape_of(const lpdec_code *const *codes, int ncodes) {
     s.dv = (codes[0]->dc.nvc == 1) ? codes[0]->dc.vc_deg[0] : 0;
     for (int c = 1; c < ncodes; ++c)
         if (codes[c]->dc.nvc != 1 || codes[c]->dc.vc_deg[0] != s.dv) s.dv = 0;
+    s.dreg = codes[0]->dc.dmin == codes[0]->dc.dmax ? codes[0]->dc.dmin : 0;
+    for (int c = 1; c < ncodes; ++c)
+        if (codes[c]->dc.dmin != s.dreg || codes[c]->dc.dmax != s.dreg) s.dreg = 0;
     return s;
 }
 
@@ -396,6 +400,36 @@ bool resident_config(const Shape &s, LaunchConfig *cfg, int variant = -1) {
     return true;
 }
 
+// Large codes with the accumulator exchange whose checks all have degree 6 or 8
+// may run k_decode_acc, which holds the first KR chunks of each wave in registers
+// from phase A to phase C and walks the others one chunk ahead (KR = -1: k_decode,
+// which walks every chunk without prefetch).  KR is bounded by the 128 registers a
+// lane has at 16 waves per workgroup (the persistent-global form keeps its held
+// chunks live across the whole iteration, so it holds fewer).  variant < 0 picks
+// the default, else the variant-th candidate (clamped).  Returns KR.
+int acc_held_chunks(const Shape &s, bool persistent, int variant, int *nvariants = nullptr) {
+    static const int kStreamed6[] = {-1, 0, 2}, kStreamed8[] = {-1, 0, 2}, kPersist6[] = {-1, 0, 1},
+                     kPersist8[] = {-1, 0, 1};
+    // defaults [persistent][degree 8] from the precision batches (8192 frames at
+    // 2.5 dB): streamed (3,6) n = 16384 49.8 / 51.2 / 53.8 ms for KR = -1 / 0 / 2,
+    // (4,8) 164.5 / 160.2 / 187.5 ms; persistent-global (3,6) 38.0 / 37.5 / 35.5 ms
+    // for KR = -1 / 0 / 1, (4,8) 125.4 / 113.0 / 105.3 ms
+    static const int kDefault[2][2] = {{0, 1}, {2, 2}};
+    const int *t = nullptr;
+    int nt = 0;
+    if (s.dreg == 6) {
+        t = persistent ? kPersist6 : kStreamed6;
+        nt = 3;
+    } else if (s.dreg == 8) {
+        t = persistent ? kPersist8 : kStreamed8;
+        nt = 3;
+    }
+    if (nvariants) *nvariants = t && s.ncodes == 1 ? nt : 0;
+    if (!t || s.ncodes != 1) return -1;
+    const int v = variant < 0 ? kDefault[persistent][s.dreg == 8] : std::min(variant, nt - 1);
+    return t[v];
+}
+
 // Where the slot exchange of the non-resident forms lives: LDS float slots when
 // 4 (E + n) bytes fit, else LDS fixed-point accumulators (8 n bytes), else global.
 int slot_mode_for(const Shape &s, size_t *lds_bytes) {
@@ -406,7 +440,7 @@ int slot_mode_for(const Shape &s, size_t *lds_bytes) {
     return 0;
 }
 
-void persistent_global_config(const Shape &s, LaunchConfig *cfg) {
+void persistent_global_config(const Shape &s, LaunchConfig *cfg, int variant = -1) {
     cfg->form = Form::PersistentGlobal;
     cfg->cpt_tmpl = 0;
     cfg->vpt_tmpl = 0;
@@ -418,6 +452,9 @@ void persistent_global_config(const Shape &s, LaunchConfig *cfg) {
     cfg->lds_E = s.Emax;
     cfg->slot_stride = s.Emax;
     cfg->state_stride = s.Eint_max;
+    cfg->acc_kr = cfg->slot_mode == 2 ? acc_held_chunks(s, true, variant) : -1;
+    cfg->acc = cfg->acc_kr >= 0;
+    cfg->acc_d = cfg->acc ? s.dreg : 0;
 }
 
 // Streamed variants (tuning value): 0 re-reads each chunk's z, u from HBM in every
@@ -446,6 +483,9 @@ void streamed_config(const Shape &s, bool half, LaunchConfig *cfg, int variant =
     cfg->lds_E = s.Emax;
     cfg->slot_stride = s.Emax;
     cfg->state_stride = 0;
+    cfg->acc_kr = cfg->slot_mode == 2 ? acc_held_chunks(s, false, variant) : -1;
+    cfg->acc = cfg->acc_kr >= 0;
+    cfg->acc_d = cfg->acc ? s.dreg : 0;
 }
 
 // Workgroups of this configuration one compute unit can hold at once, from the
@@ -482,6 +522,31 @@ int occupancy_grid(const LaunchConfig &cfg, int frames, const lpdec_code *code) 
 
 lpdec_status check_params(const lpdec_params *p);
 
+// Per-workgroup scratch of the persistent forms (bytes per workgroup; 0: unused):
+// gamma/mu staged in internal variable order, the persistent-global state, the
+// previous x of the accumulator exchange and the global slots.
+struct WgBytes {
+    size_t gmu = 0, state = 0, xprev = 0, slots = 0;
+    size_t total() const { return gmu + state + xprev + slots; }
+};
+WgBytes wg_bytes(const Shape &s, const LaunchConfig &cfg) {
+    WgBytes b;
+    const bool pg = cfg.form == Form::PersistentGlobal;
+    if (s.permuted && cfg.vpt_tmpl == 0) b.gmu = sizeof(float) * (size_t)s.nmax;
+    if (pg) {
+        b.state = 2 * sizeof(float) * (size_t)cfg.state_stride;
+        if (cfg.slot_mode == 2) b.xprev = sizeof(unsigned) * (size_t)s.nmax;
+        if (cfg.slot_mode == 0) b.slots = sizeof(float) * (size_t)cfg.slot_stride;
+    }
+    return b;
+}
+
+// Host bytes of the per-frame metadata of a scattered single-code launch (code
+// table, LLR and x offsets, code indices).
+size_t meta_host_bytes(int nframes) {
+    return ((sizeof(DevCode) + 255) / 256) * 256 + (size_t)nframes * (2 * sizeof(int64_t) + sizeof(int32_t));
+}
+
 // The form and launch configuration a decode of these codes with these
 // parameters uses (the mode resolution of every decode entry point).
 lpdec_status resolve_config(const Shape &s, const lpdec_params &p, bool scattered, LaunchConfig *cfg,
@@ -497,7 +562,8 @@ lpdec_status resolve_config(const Shape &s, const lpdec_params &p, bool scattere
             return fail(LPDEC_EUNSUPPORTED, "the register-resident form does not fit this code");
         mode = LPDEC_MODE_PERSISTENT_GLOBAL;
     }
-    if (mode == LPDEC_MODE_PERSISTENT_GLOBAL) persistent_global_config(s, cfg);
+    if (mode == LPDEC_MODE_PERSISTENT_GLOBAL)
+        persistent_global_config(s, cfg, code ? code->tune_variant[static_cast<int>(Form::PersistentGlobal)] : -1);
     if (mode == LPDEC_MODE_STREAMED) {
         if (scattered)
             return fail(LPDEC_EUNSUPPORTED, "the streamed form decodes one dense batch of one code per call");
@@ -555,8 +621,8 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
     const bool half = p.storage == LPDEC_STORAGE_FP16;
     st = resolve_config(s, p, ncodes > 1 || code_of_frame || llr_off || done, &cfg, codes[0]);
     if (st != LPDEC_OK) return st;
-    if (arena && (ncodes > 1 || code_of_frame || llr_off || done))
-        return fail(LPDEC_EINVAL, "lent scratch serves dense single-code batches only");
+    if (arena && (ncodes > 1 || code_of_frame || ((llr_off || x_off || done) && !arena->host)))
+        return fail(LPDEC_EINVAL, "lent scratch serves single-code batches (scattered ones with host staging)");
     if (arena && cfg.form == Form::Streamed)
         return fail(LPDEC_EUNSUPPORTED,
                     "the allocation-free decode runs the persistent forms only (FP32 storage, mode AUTO, RESIDENT "
@@ -584,10 +650,12 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
     fb.iters_out = iters_out;
     fb.flags_out = flags_out;
     fb.done = done;
+    size_t meta_bytes = 0;  // device bytes of the per-frame metadata (lent scratch: carved after the queue)
     if (ncodes > 1 || code_of_frame || llr_off) {
         // Metadata goes through pinned staging owned by the workspace.  The
         // previous call on this workspace may still be copying from it, so wait
         // for that call first (the source must outlive the asynchronous copy).
+        // Lent scratch brings its own staging, which its owner keeps idle.
         const size_t tbl_bytes = ((sizeof(DevCode) * ncodes + 255) / 256) * 256;
         // frames of codes of different sizes are handed out largest code first, so
         // that the launch ends on short frames (less idle time in its tail); the
@@ -598,16 +666,26 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
                              (cfg.form == Form::Resident || cfg.form == Form::PersistentGlobal);
         const size_t bytes = tbl_bytes + (size_t)nframes * (2 * sizeof(int64_t) + sizeof(int32_t)) +
                              (ordered ? (size_t)nframes * sizeof(int32_t) : 0);
-        if (ws.last) HIP_TRY(hipEventSynchronize(ws.last));
-        if (ws.host_meta_bytes < bytes) {
-            if (ws.host_meta) HIP_TRY(hipHostFree(ws.host_meta));
-            ws.host_meta = nullptr;
-            ws.host_meta_bytes = 0;
-            HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&ws.host_meta), bytes, hipHostMallocDefault));
-            ws.host_meta_bytes = bytes;
+        char *h, *d;
+        meta_bytes = (bytes + 255) / 256 * 256;
+        if (arena) {
+            if (bytes > arena->host_bytes || 256 + meta_bytes > arena->bytes)
+                return fail(LPDEC_EUNSUPPORTED, "per-frame metadata of %zu bytes exceeds the lent scratch", bytes);
+            h = arena->host;
+            d = arena->base + 256;
+        } else {
+            if (ws.last) HIP_TRY(hipEventSynchronize(ws.last));
+            if (ws.host_meta_bytes < bytes) {
+                if (ws.host_meta) HIP_TRY(hipHostFree(ws.host_meta));
+                ws.host_meta = nullptr;
+                ws.host_meta_bytes = 0;
+                HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&ws.host_meta), bytes, hipHostMallocDefault));
+                ws.host_meta_bytes = bytes;
+            }
+            HIP_TRY(ws.frame_meta.ensure(bytes));
+            h = ws.host_meta;
+            d = static_cast<char *>(ws.frame_meta.p);
         }
-        HIP_TRY(ws.frame_meta.ensure(bytes));
-        char *h = ws.host_meta;
         for (int c = 0; c < ncodes; ++c) std::memcpy(h + sizeof(DevCode) * c, &codes[c]->dc, sizeof(DevCode));
         int64_t *h_loff = reinterpret_cast<int64_t *>(h + tbl_bytes);
         int64_t *h_xoff = h_loff + nframes;
@@ -624,8 +702,7 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
                 return codes[code_of_frame[a]]->dc.E > codes[code_of_frame[b]]->dc.E;
             });
         }
-        HIP_TRY(hipMemcpyAsync(ws.frame_meta.p, h, bytes, hipMemcpyHostToDevice, stream));
-        char *d = static_cast<char *>(ws.frame_meta.p);
+        HIP_TRY(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, stream));
         codes_dev = reinterpret_cast<const DevCode *>(d);
         fb.llr_off = reinterpret_cast<const int64_t *>(d + tbl_bytes);
         fb.x_off = fb.llr_off + nframes;
@@ -656,17 +733,15 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
     if (cfg.form == Form::Resident || cfg.form == Form::PersistentGlobal) {
         cfg.grid = occupancy_grid(cfg, nframes, codes[0]);
         // per-workgroup scratch (bytes per workgroup of each buffer; 0: not used)
-        const bool need_gmu = s.permuted && cfg.vpt_tmpl == 0;  // gamma/mu staged in internal variable order
+        const WgBytes wb = wg_bytes(s, cfg);
+        const bool need_gmu = wb.gmu > 0;
         const bool pg = cfg.form == Form::PersistentGlobal;
-        const size_t b_gmu = need_gmu ? sizeof(float) * (size_t)s.nmax : 0;
-        const size_t b_state = pg ? 2 * sizeof(float) * (size_t)cfg.state_stride : 0;
-        const size_t b_xprev = (pg && cfg.slot_mode == 2) ? sizeof(unsigned) * (size_t)s.nmax : 0;
-        const size_t b_slots = (pg && cfg.slot_mode == 0) ? sizeof(float) * (size_t)cfg.slot_stride : 0;
+        const size_t b_gmu = wb.gmu, b_state = wb.state, b_xprev = wb.xprev, b_slots = wb.slots;
         void *p_queue, *p_gmu, *p_state, *p_xprev, *p_slots;
         if (arena) {
-            // queue counter, then each buffer 256-byte aligned; the grid is cut so
-            // that all of them fit (a frame's result does not depend on the grid)
-            const size_t per_wg = b_gmu + b_state + b_xprev + b_slots, fixed = 256 + 4 * 255;
+            // queue counter, metadata, then each buffer 256-byte aligned; the grid is
+            // cut so that all of them fit (a frame's result does not depend on the grid)
+            const size_t per_wg = b_gmu + b_state + b_xprev + b_slots, fixed = 256 + meta_bytes + 4 * 255;
             if (per_wg > 0) {
                 if (fixed + per_wg > arena->bytes)
                     return fail(LPDEC_EUNSUPPORTED,
@@ -683,7 +758,7 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
                 return per ? q : nullptr;
             };
             p_queue = arena->base;
-            off = 256;
+            off = 256 + meta_bytes;
             p_gmu = carve(b_gmu);
             p_state = carve(b_state);
             p_xprev = carve(b_xprev);
@@ -800,6 +875,34 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
     return LPDEC_OK;
 }
 
+lpdec_status lpdec_scratch_need(const lpdec_code *code, const lpdec_params *pin, int nframes, bool scattered,
+                                ScratchNeed *out) {
+    lpdec_params p = pin ? *pin : lpdec_default_params();
+    lpdec_status st = check_params(&p);
+    if (st != LPDEC_OK) return st;
+    const Shape s = shape_of(&code, 1);
+    LaunchConfig cfg{};
+    st = resolve_config(s, p, scattered, &cfg, code);
+    if (st != LPDEC_OK) return st;
+    *out = ScratchNeed{};
+    if (cfg.form == Form::Streamed) {
+        out->streamed = true;
+        return LPDEC_OK;
+    }
+    // the grid of a launch of nframes frames (two frames per workgroup only pair
+    // when every CU gets two, as in lpdec_decode_core)
+    if (cfg.pair && code->tune_variant[static_cast<int>(Form::Resident)] < 1) {
+        const DeviceInfo di = device_info();
+        if (nframes < 2 * (di.cus > 0 ? di.cus : 256)) resident_config(s, &cfg, 0);
+    }
+    cfg.grid = occupancy_grid(cfg, std::max(1, nframes), code);
+    out->per_wg = wg_bytes(s, cfg).total();
+    out->host = scattered ? meta_host_bytes(nframes) : 0;
+    out->fixed = 256 + (out->host + 255) / 256 * 256 + 4 * 255;
+    out->grid = cfg.grid;
+    return LPDEC_OK;
+}
+
 // ---------------------------------------------------------------------------
 // C ABI
 
@@ -888,7 +991,15 @@ lpdec_status lpdec_code_launch_info(const lpdec_code *code, const lpdec_params *
     out->runtime_blocks_per_cu = q.occupancy;
     out->resource_blocks_per_cu = resource_blocks_per_cu(cfg, q);
     out->blocks_per_cu = blocks_per_cu(cfg, code);
-    if (cfg.form == Form::Streamed) out->variant = cfg.cpt_tmpl == 0 ? 0 : (cfg.staged ? 2 : 1);
+    int nacc = 0;
+    if (cfg.form != Form::Resident && cfg.slot_mode == 2)
+        acc_held_chunks(shape_of(&code, 1), cfg.form == Form::PersistentGlobal, 0, &nacc);
+    if (nacc > 0) {  // index of the held-chunk count among the code's candidates
+        const Shape s = shape_of(&code, 1);
+        out->variant = 0;
+        for (int v = 0; v < nacc; ++v)
+            if (acc_held_chunks(s, cfg.form == Form::PersistentGlobal, v) == cfg.acc_kr) out->variant = v;
+    } else if (cfg.form == Form::Streamed) out->variant = cfg.cpt_tmpl == 0 ? 0 : (cfg.staged ? 2 : 1);
     else if (cfg.form == Form::Resident && cfg.dclass == 0 && cfg.dv == 3 && cfg.cpt_tmpl == 2)
         out->variant = cfg.pair ? 1 : 0;
     else out->variant = -1;
@@ -925,7 +1036,10 @@ lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, c
         LaunchConfig probe{};
         res_pair = resident_config(shape_of(&one, 1), &probe, 1) && probe.pair;
     }
-    const int nvar = cfg.form == Form::Streamed ? 3 : (res_pair ? 2 : 1);
+    int nacc = 0;  // held-chunk candidates of the large-code kernel
+    if (cfg.form != Form::Resident && cfg.slot_mode == 2)
+        acc_held_chunks(shape_of(&one, 1), cfg.form == Form::PersistentGlobal, 0, &nacc);
+    const int nvar = nacc > 0 ? nacc : (cfg.form == Form::Streamed ? 3 : (res_pair ? 2 : 1));
     hipStream_t stream = static_cast<hipStream_t>(stream_v);
     const size_t n = (size_t)code->dc.n;
     float *x = nullptr;
@@ -946,7 +1060,7 @@ lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, c
         for (int v = 0; v < nvar; ++v) {
             const int var = nvar == 1 ? -1 : v;
             code->tune_variant[f] = var;
-            if (cfg.form == Form::Streamed) {  // a streamed variant the code does not allow falls back: skip it
+            if (cfg.form == Form::Streamed && nacc == 0) {  // a streamed variant the code does not allow falls back: skip it
                 LaunchConfig probe{};
                 streamed_config(shape_of(&one, 1), p.storage == LPDEC_STORAGE_FP16, &probe, var);
                 const int got = probe.cpt_tmpl == 0 ? 0 : (probe.staged ? 2 : 1);

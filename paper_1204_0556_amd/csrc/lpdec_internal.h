@@ -133,6 +133,11 @@ struct LaunchConfig {
     // wave (the code plan's wave) that physical wave p hosts, in bits 4p..4p+3 (0xF: none)
     bool pair;
     unsigned long long pair_host[2];
+    // large check-regular codes with the accumulator exchange: k_decode_acc (acc)
+    // with the common check degree and the chunks per wave held in registers
+    bool acc;
+    int acc_d;
+    int acc_kr;
 };
 
 hipError_t launch_decode(const LaunchConfig &cfg, const DevCode *codes_dev, const FrameBatch &fb,

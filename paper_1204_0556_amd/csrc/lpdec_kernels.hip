@@ -324,31 +324,24 @@ __device__ __forceinline__ float x_update(const float *slots, const VarLoc &L, f
 // Exact, order-independent per-variable sums for codes whose slot array does not
 // fit in LDS: each replica difference w is converted to signed 32.32 fixed point,
 // floor(w 2^32) (exact for 2^-9 <= |w| < 2^31; smaller magnitudes are rounded
-// toward -infinity to a multiple of 2^-32; |w| >= 2^31 saturates to the largest
-// value of its sign), and accumulated with 64-bit integer LDS atomics.  Integer
-// addition is associative, so the sum does not depend on the order the lanes
-// arrive in.  Both conversions use integer operations only: the float's
-// significand is shifted into place by its exponent.
+// toward -infinity to a multiple of 2^-32; w is first clamped to [-2^31, 2^31 - 128],
+// the largest float below 2^31), and accumulated with 64-bit integer LDS atomics.
+// Integer addition is associative, so the sum does not depend on the order the
+// lanes arrive in.  The conversion is branch-free FP32/integer arithmetic: the
+// magnitude splits exactly into its integer part and its fraction (the difference
+// of a float and its floor is exact), the fraction scaled by 2^32 is an exact float
+// whose integer part is the low word, and a negative value is the two's complement
+// of the magnitude rounded up (bits below 2^-32 make the floor one step lower).
 __device__ __forceinline__ unsigned long long to_fixed(float w) {
-    const unsigned b = __float_as_uint(w);
-    const int e = (int)((b >> 23) & 0xffu);  // biased exponent (0: zero or subnormal)
-    const unsigned long long m = (b & 0x7fffffu) | (e != 0 ? 0x800000u : 0u);
-    const int sh = max(e, 1) - 118;  // |w| 2^32 = m 2^sh  (2^(e-127-23+32))
-    unsigned long long mag;
-    bool cut;  // nonzero bits shifted out
-    if (sh >= 0) {
-        mag = m << min(sh, 39);
-        cut = false;
-    } else {
-        const int r = min(-sh, 63);
-        mag = m >> r;
-        cut = (m & ((1ull << r) - 1ull)) != 0ull;
-    }
-    const bool neg = (b >> 31) != 0u;
-    // floor: a negative value with bits cut off rounds away from zero
-    unsigned long long v = neg ? 0ull - (mag + (cut ? 1ull : 0ull)) : mag;
-    if (e >= 158) v = neg ? 0x8000000000000000ull : 0x7fffffff00000000ull;  // |w| >= 2^31
-    return v;
+    const float c = __builtin_amdgcn_fmed3f(w, -2147483648.0f, 2147483520.0f);
+    const float a = fabsf(c);
+    const float ah = floorf(a);
+    const float r = (a - ah) * 4294967296.0f;  // in [0, 2^32)
+    const unsigned hi = (unsigned)ah, lo = (unsigned)r;
+    const bool cut = r != truncf(r);
+    const unsigned m = (unsigned)(__float_as_int(c) >> 31);  // all ones when negative
+    const unsigned long long v = ((unsigned long long)(hi ^ m) << 32) | (lo ^ m);
+    return v + ((m != 0u && !cut) ? 1ull : 0ull);
 }
 // The sum back to FP32: a correctly rounded conversion of the signed 64-bit value
 // (integer normalisation, no FP64), then an exact scale by 2^-32.
@@ -1421,6 +1414,426 @@ k_decode_pair(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, S
     else if (live1) tail(S1, f1, it1);
 }
 
+// ---------------------------------------------------------------------------
+// Large codes whose checks all have one degree D and whose exchange goes through
+// the LDS fixed-point accumulators (the slot array does not fit in LDS): the
+// persistent-global and streamed forms with the first KR chunks of each wave held
+// in registers from phase A to phase C.  k_decode's chunk walk reads a chunk's z, u
+// in phase A (for the sums) and again in phase C (for the update); here a held
+// chunk is read once per iteration (streamed form) or never leaves the registers
+// while its frame runs (persistent-global form), and only a wave's chunks beyond
+// the first KR are walked as before.  The arithmetic, the order of the residual
+// sums and the exchange are those of k_decode, so results are bitwise the same.
+// Chunks are padded to 64 lanes in every array, so a held chunk's rows are loaded
+// for all lanes without a branch (padding lanes take no part in the update).
+template <int D, int KR, bool HALF, bool PERSIST>
+__global__ void __launch_bounds__(kMaxThreads, 1)
+k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateIO sio, StreamArgs sa,
+             int state_stride) {
+    static_assert(!PERSIST || !HALF, "FP16 storage is a streamed-form option");
+    static_assert(KR >= 0, "held chunks per wave");
+    constexpr int KH = KR > 0 ? KR : 1;  // register arrays of the held chunks
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    __shared__ float s_red[2][2][kMaxWaves];
+    __shared__ int s_frame;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int NT = blockDim.x;
+    const int NW = NT >> 6;
+    const DevCode &C = codes[0];
+    const int W = C.waves, cpt = C.cpt;
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(lds);
+    const float *xs = lds + 1;  // x sits in each accumulator's high word (stride 2)
+    unsigned *xprev = PERSIST ? sa.gxprev + (size_t)blockIdx.x * sa.gmu_stride : nullptr;
+    const float thr = ip.tol2 * (float)C.E;
+
+    // held chunks k < KR of this wave: chunk wave + k W (a missing one repeats the
+    // wave's first chunk, whose lanes then take no part)
+    int hoff[KH];
+    bool hval[KH];
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+        const int c = wave + k * W;
+        const bool has = k < cpt && c < C.nchunks;
+        const ChunkDesc h = chunk_desc(C, has ? c : wave);
+        hoff[k] = h.off;
+        hval[k] = has && lane < h.cnt;
+    }
+    float zr[KH][D], ur[KH][D];
+
+    int sbase = (int)blockIdx.x - kWave * (int)gridDim.x;
+    unsigned long long smask = 0ull;
+    auto next_active = [&]() -> int {
+        for (;;) {
+            if (smask) {
+                const int j = __builtin_ctzll(smask);
+                smask &= smask - 1ull;
+                return sbase + j * (int)gridDim.x;
+            }
+            sbase += kWave * (int)gridDim.x;
+            if (sbase >= fb.nframes) return fb.nframes;
+            const int fj = sbase + lane * (int)gridDim.x;
+            const bool act = fj < fb.nframes && !sa.st[fj].done;
+            smask = __ballot(act);
+        }
+    };
+    if constexpr (!PERSIST) {
+        if (blockIdx.x == 0 && tid == 0) sa.active_count[(ip.launch + 1) & 1] = 0;  // next launch's counter
+    }
+    for (;;) {
+        int f;
+        if constexpr (PERSIST) {
+            if (tid == 0) {
+                const int q = atomicAdd(fb.queue, 1);
+                s_frame = (fb.order && q < fb.nframes) ? fb.order[q] : q;
+            }
+            __syncthreads();
+            f = __builtin_amdgcn_readfirstlane(s_frame);
+            __syncthreads();
+        } else {
+            f = next_active();
+        }
+        if (f >= fb.nframes) break;
+        const int64_t loff = fb.llr_off ? fb.llr_off[f] : (int64_t)f * C.n;
+        const float *gam = fb.llr + loff;
+        float *gmu_row = sa.gmu ? sa.gmu + (size_t)(PERSIST ? blockIdx.x : f) * sa.gmu_stride : nullptr;
+        if constexpr (PERSIST) {
+            if (!C.var_identity) {
+                for (int i = tid; i < C.n; i += NT) gmu_row[i] = gam[C.var_orig[i]] * ip.mu_inv;
+                __syncthreads();  // global staging, read by other threads in phase B
+            }
+            if (frame_invalid(fb, f)) {
+                for (int i = tid; i < C.n; i += NT)
+                    fb.x_out[(fb.x_off ? fb.x_off[f] : (int64_t)f * C.n) + i] = 0.5f;
+                __syncthreads();
+                if (tid == 0) {
+                    fb.iters_out[f] = 0;
+                    fb.flags_out[f] = 0x80;
+                    if (fb.done) {
+                        __threadfence_system();
+                        __hip_atomic_store(fb.done + f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                    }
+                }
+                __syncthreads();
+                continue;
+            }
+        }
+        const size_t sb = PERSIST ? (size_t)blockIdx.x * state_stride : (size_t)f * C.E_int;
+        void *gz = HALF ? (void *)(static_cast<__half *>(sa.z) + sb) : (void *)(static_cast<float *>(sa.z) + sb);
+        void *gu = HALF ? (void *)(static_cast<__half *>(sa.u) + sb) : (void *)(static_cast<float *>(sa.u) + sb);
+
+        // initial state (persistent-global form; the streamed form has its own kernel):
+        // held chunks in registers, walked chunks in the workgroup's scratch
+        if constexpr (PERSIST) {
+            const size_t fb0 = (size_t)f * C.E;
+#pragma unroll
+            for (int k = 0; k < KR; ++k)
+#pragma unroll
+                for (int e = 0; e < D; ++e) {
+                    float z0 = 0.0f, u0 = 0.0f;
+                    if (sio.z_in && hval[k]) {
+                        const int ce = C.edge_csr[hoff[k] + e * kWave + lane];
+                        z0 = sio.z_in[fb0 + ce];
+                        u0 = sio.u_in[fb0 + ce];
+                    }
+                    zr[k][e] = z0;
+                    ur[k][e] = u0;
+                }
+            for (int k = KR; k < cpt; ++k) {
+                const int c = wave + k * W;
+                if (c >= C.nchunks) break;
+                const ChunkDesc h = chunk_desc(C, c);
+                for (int e = 0; e < D; ++e) {
+                    const int p = h.off + e * kWave + lane;
+                    float z0 = 0.0f, u0 = 0.0f;
+                    if (sio.z_in && lane < h.cnt) {
+                        const int ce = C.edge_csr[p];
+                        z0 = sio.z_in[fb0 + ce];
+                        u0 = sio.u_in[fb0 + ce];
+                    }
+                    st_state<false>(gz, p, z0);
+                    st_state<false>(gu, p, u0);
+                }
+            }
+        }
+        // fresh accumulators (and previous x) for this frame
+        for (int i = tid; i < C.n; i += NT) {
+            acc[i] = 0ull;
+            if constexpr (PERSIST) as_global_rw(xprev)[i] = 0u;
+        }
+        wg_barrier<true>();
+
+        // A: the replica differences z - u into the accumulators
+        // streamed form: this frame's z, u of held chunk k into its registers
+        auto load_held = [&](int k) {
+#pragma unroll
+            for (int e = 0; e < D; ++e) {
+                const size_t p = hoff[k] + e * kWave + lane;
+                zr[k][e] = ld_state<HALF>(gz, p);
+                ur[k][e] = ld_state<HALF>(gu, p);
+            }
+        };
+        // the walked chunks k >= KR of this wave (chunk wave + k W), one chunk ahead:
+        // chunk k + 1's z, u and metadata are loaded before chunk k is used, so a
+        // wave keeps two chunks' loads in flight (all lanes load; padding lanes of a
+        // chunk exist in every array and take no part)
+        struct Walk {
+            int k, off, cnt;
+            bool has;
+        };
+        auto walk_at = [&](int k) -> Walk {
+            const int c = wave + k * W;
+            const bool has = k < cpt && c < C.nchunks;  // wave-uniform
+            const ChunkDesc h = has ? chunk_desc(C, c) : ChunkDesc{0, 0, 0};
+            return Walk{k, h.off, h.cnt, has};
+        };
+        auto walk_load = [&](const Walk &w, float *zz, float *uu, uint32_t *mm) {
+#pragma unroll
+            for (int e = 0; e < D; ++e) {
+                const size_t p = w.off + e * kWave + lane;
+                zz[e] = ld_state<HALF>(gz, p);
+                uu[e] = ld_state<HALF>(gu, p);
+                mm[e] = as_global(C.edge_meta)[p];
+            }
+        };
+        auto phase_a = [&]() {
+            if constexpr (KR > 0) {
+                // held chunks, one ahead: chunk k + 1's loads are issued before chunk
+                // k's accumulation waits for its own
+                uint32_t mcur[D], mnext[D];
+                if constexpr (!PERSIST) load_held(0);
+                load_meta<D>(mcur, C.edge_meta, hoff[0], D, lane);
+#pragma unroll
+                for (int k = 0; k < KR; ++k) {
+                    if (k + 1 < KR) {
+                        if constexpr (!PERSIST) load_held(k + 1);
+                        load_meta<D>(mnext, C.edge_meta, hoff[k + 1], D, lane);
+                    }
+                    if (hval[k]) {
+#pragma unroll
+                        for (int e = 0; e < D; ++e)
+                            atomicAdd(acc + (mcur[e] & 0xffffu), to_fixed(zr[k][e] - ur[k][e]));
+                    }
+#pragma unroll
+                    for (int e = 0; e < D; ++e) mcur[e] = mnext[e];
+                }
+            }
+            Walk cur = walk_at(KR);
+            float zc[D], uc[D];
+            uint32_t mc[D];
+            if (cur.has) walk_load(cur, zc, uc, mc);
+            while (cur.has) {
+                const Walk nxt = walk_at(cur.k + 1);
+                float zn[D], un[D];
+                uint32_t mn[D];
+                if (nxt.has) walk_load(nxt, zn, un, mn);
+                if (lane < cur.cnt) {
+#pragma unroll
+                    for (int e = 0; e < D; ++e) atomicAdd(acc + (mc[e] & 0xffffu), to_fixed(zc[e] - uc[e]));
+                }
+#pragma unroll
+                for (int e = 0; e < D; ++e) {
+                    zc[e] = zn[e];
+                    uc[e] = un[e];
+                    mc[e] = mn[e];
+                }
+                cur = nxt;
+            }
+        };
+        // B: x_i from its accumulator (less the previous x kept in the high word)
+        auto phase_b = [&]() {
+            const float *gsrc = C.var_identity ? gam : gmu_row;
+            const float gscale = C.var_identity ? ip.mu_inv : 1.0f;
+            for (int i = tid; i < C.n; i += NT) {
+                const unsigned prev = PERSIST ? as_global(xprev)[i] : 0u;
+                const unsigned long long a = acc[i] - ((unsigned long long)prev << 32);
+                const float inv = (C.dv > 0) ? C.dv_inv
+                                             : __int_as_float(as_global(reinterpret_cast<const int *>(C.var_info))[2 * i + 1]);
+                const float x = clamp01((from_fixed(a) - as_global(gsrc)[i] * gscale) * inv);
+                acc[i] = (unsigned long long)__float_as_uint(x) << 32;
+                if constexpr (PERSIST) as_global_rw(xprev)[i] = __float_as_uint(x);
+            }
+        };
+        // C: check updates (held chunks from registers, walked chunks from memory)
+        auto phase_c = [&](float &rp, float &rd) {
+            if constexpr (KR > 0) {
+                uint32_t mcur[D], mnext[D];
+                load_meta<D>(mcur, C.edge_meta, hoff[0], D, lane);
+#pragma unroll
+                for (int k = 0; k < KR; ++k) {
+                    if (k + 1 < KR) load_meta<D>(mnext, C.edge_meta, hoff[k + 1], D, lane);
+                    if (hval[k]) {
+                        check_update<D, 2>(zr[k], ur[k], mcur, xs, ip.rho, rp, rd);
+                        if constexpr (!PERSIST) {
+#pragma unroll
+                            for (int e = 0; e < D; ++e) {
+                                const size_t p = hoff[k] + e * kWave + lane;
+                                st_state<HALF>(gz, p, zr[k][e]);
+                                st_state<HALF>(gu, p, ur[k][e]);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int e = 0; e < D; ++e) mcur[e] = mnext[e];
+                }
+            }
+            Walk cur = walk_at(KR);
+            float zc[D], uc[D];
+            uint32_t mc[D];
+            if (cur.has) walk_load(cur, zc, uc, mc);
+            while (cur.has) {
+                const Walk nxt = walk_at(cur.k + 1);
+                float zn[D], un[D];
+                uint32_t mn[D];
+                if (nxt.has) walk_load(nxt, zn, un, mn);
+                if (lane < cur.cnt) {
+                    check_update<D, 2>(zc, uc, mc, xs, ip.rho, rp, rd);
+#pragma unroll
+                    for (int e = 0; e < D; ++e) {
+                        const size_t p = cur.off + e * kWave + lane;
+                        st_state<HALF>(gz, p, zc[e]);
+                        st_state<HALF>(gu, p, uc[e]);
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < D; ++e) {
+                    zc[e] = zn[e];
+                    uc[e] = un[e];
+                    mc[e] = mn[e];
+                }
+                cur = nxt;
+            }
+        };
+        auto publish = [&](int buf, float rp, float rd) {
+            rp = wave_sum(rp);
+            rd = wave_sum(rd);
+            if (lane == 0) {
+                s_red[buf][0][wave] = rp;
+                s_red[buf][1][wave] = rd;
+            }
+        };
+        auto converged = [&](int buf) -> bool {  // identical result in every wave
+            const float a = lane < NW ? s_red[buf][0][lane] : 0.0f;
+            const float b = lane < NW ? s_red[buf][1][lane] : 0.0f;
+            return wave_sum(a) < thr && wave_sum(b) < thr;
+        };
+
+        int iters;
+        bool conv = false;
+        if constexpr (PERSIST) {
+            // iteration it = B, C, then the next iteration's A (after a barrier: A adds
+            // into the entries C reads x from); the stopping test reads the residuals
+            // C published, after the barrier that follows that A
+            int it = 1;
+            phase_a();
+            wg_barrier<true>();
+            for (;; ++it) {
+                phase_b();
+                wg_barrier<true>();
+                float rp = 0.0f, rd = 0.0f;
+                phase_c(rp, rd);
+                publish(it & 1, rp, rd);
+                wg_barrier<true>();
+                phase_a();
+                wg_barrier<true>();
+                if (__builtin_amdgcn_readfirstlane(converged(it & 1))) { conv = true; break; }
+                if (it >= ip.max_iter) break;
+            }
+            iters = conv ? it : ip.max_iter;
+            // the last phase A accumulated into the entries holding x: restore the last x
+            for (int i = tid; i < C.n; i += NT) acc[i] = (unsigned long long)as_global(xprev)[i] << 32;
+            __syncthreads();
+        } else {
+            const int it = ip.launch + 1;
+            phase_a();
+            wg_barrier<true>();
+            phase_b();
+            wg_barrier<true>();
+            float rp = 0.0f, rd = 0.0f;
+            phase_c(rp, rd);
+            publish(0, rp, rd);
+            wg_barrier<true>();
+            conv = converged(0);
+            iters = it;
+            const bool fin = __builtin_amdgcn_readfirstlane(conv || it >= ip.max_iter);
+            if (tid == 0) {
+                sa.st[f].iter = it;
+                if (fin) sa.st[f].done = 1;
+                else atomicAdd(sa.active_count + (ip.launch & 1), 1);
+            }
+            if (!fin) {
+                wg_barrier<true>();  // LDS reuse by the next frame of this workgroup
+                continue;
+            }
+        }
+
+        // -- epilogue: x, iteration count and certificate flags ----------------------
+        const int64_t xoff = fb.x_off ? fb.x_off[f] : (int64_t)f * C.n;
+        float frac = 0.0f;
+        for (int i = tid; i < C.n; i += NT) {
+            const float x = xs[2 * i];
+            fb.x_out[xoff + (C.var_identity ? i : C.var_orig[i])] = x;
+            frac = fmaxf(frac, fminf(x, 1.0f - x));
+        }
+        bool odd = false;
+        for (int c = wave; c < C.nchunks; c += W) {
+            const ChunkDesc h = chunk_desc(C, c);
+            if (lane < h.cnt) {
+                bool par = false;
+                for (int e = 0; e < D; ++e) par ^= (xs[2 * (C.edge_meta[h.off + e * kWave + lane] & 0xffffu)] >= 0.5f);
+                odd |= par;
+            }
+        }
+        // frac > 1e-3 exactly: 1e-3f is the least float above 1e-3
+        const bool nonint = frac >= 1e-3f;
+        const int any_odd = __syncthreads_or(odd);
+        const int any_nonint = __syncthreads_or(nonint);
+        if (tid == 0) {
+            uint8_t fl = conv ? 0x01 : 0x00;
+            if (!any_nonint) fl |= 0x02;
+            if (!any_odd) fl |= 0x04;
+            if ((fl & 0x07) == 0x07) fl |= 0x08;
+            fb.iters_out[f] = iters;
+            fb.flags_out[f] = fl;
+            if (fb.done) {
+                __threadfence_system();
+                __hip_atomic_store(fb.done + f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+        // state export in CSR edge order (persistent-global form; the streamed form
+        // exports with its own kernel after the last launch)
+        if constexpr (PERSIST) {
+            if (sio.z_out) {
+                const size_t fb0 = (size_t)f * C.E;
+#pragma unroll
+                for (int k = 0; k < KR; ++k)
+#pragma unroll
+                    for (int e = 0; e < D; ++e)
+                        if (hval[k]) {
+                            const int ce = C.edge_csr[hoff[k] + e * kWave + lane];
+                            sio.z_out[fb0 + ce] = zr[k][e];
+                            sio.u_out[fb0 + ce] = ur[k][e];
+                        }
+                for (int k = KR; k < cpt; ++k) {
+                    const int c = wave + k * W;
+                    if (c >= C.nchunks) break;
+                    const ChunkDesc h = chunk_desc(C, c);
+                    if (lane < h.cnt) {
+                        for (int e = 0; e < D; ++e) {
+                            const size_t p = h.off + e * kWave + lane;
+                            const int ce = C.edge_csr[p];
+                            sio.z_out[fb0 + ce] = ld_state<false>(gz, p);
+                            sio.u_out[fb0 + ce] = ld_state<false>(gu, p);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Streamed form set-up: zero (or load) each frame's state, flag invalid frames.
 template <bool HALF>
 __global__ void __launch_bounds__(256)
@@ -1590,9 +2003,58 @@ static hipError_t go_pair(const LaunchConfig &cfg, const DevCode *codes, const F
     return hipGetLastError();
 }
 
+// large check-regular codes with the accumulator exchange (see k_decode_acc)
+template <int D, int KR, bool HALF, bool PERSIST>
+static hipError_t go_acc1(const LaunchConfig &cfg, const DevCode *codes, const FrameBatch &fb, const IterParams &ip,
+                          const StateIO &sio, const StreamArgs &sa, hipStream_t stream, KernelQuery *q) {
+    auto kern = k_decode_acc<D, KR, HALF, PERSIST>;
+    if (cfg.lds_bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg.lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    if (q) {
+        hipFuncAttributes fa{};
+        hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kern));
+        if (e != hipSuccess) return e;
+        q->vgprs = fa.numRegs;
+        q->static_lds = (int)fa.sharedSizeBytes;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&q->occupancy, kern, cfg.threads, cfg.lds_bytes);
+    }
+    hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(cfg.threads), cfg.lds_bytes, stream, codes, fb, ip, sio, sa,
+                       cfg.state_stride);
+    return hipGetLastError();
+}
+
+static hipError_t go_acc(const LaunchConfig &cfg, const DevCode *codes, const FrameBatch &fb, const IterParams &ip,
+                         const StateIO &sio, const StreamArgs &sa, hipStream_t stream, KernelQuery *q) {
+    const bool pg = cfg.form == Form::PersistentGlobal;
+    // held chunks per wave instantiated (see acc_held_chunks in lpdec_host.cpp)
+#define LPD_ACC_S(D, KR)                                                                          \
+    if (!pg && cfg.acc_d == D && cfg.acc_kr == KR) {                                              \
+        if (cfg.half) return go_acc1<D, KR, true, false>(cfg, codes, fb, ip, sio, sa, stream, q); \
+        return go_acc1<D, KR, false, false>(cfg, codes, fb, ip, sio, sa, stream, q);              \
+    }
+#define LPD_ACC_P(D, KR) \
+    if (pg && cfg.acc_d == D && cfg.acc_kr == KR) return go_acc1<D, KR, false, true>(cfg, codes, fb, ip, sio, sa, stream, q);
+    if (cfg.form == Form::Resident) return hipErrorInvalidValue;
+    LPD_ACC_S(6, 0)
+    LPD_ACC_S(6, 2)
+    LPD_ACC_S(8, 0)
+    LPD_ACC_S(8, 2)
+    LPD_ACC_P(6, 0)
+    LPD_ACC_P(6, 1)
+    LPD_ACC_P(8, 0)
+    LPD_ACC_P(8, 1)
+#undef LPD_ACC_S
+#undef LPD_ACC_P
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_decode(const LaunchConfig &cfg, const DevCode *codes_dev, const FrameBatch &fb,
                          const IterParams &ip, const StateIO &sio, const StreamArgs &sa, hipStream_t stream) {
     if (cfg.pair) return go_pair(cfg, codes_dev, fb, ip, sio, stream, nullptr);
+    if (cfg.acc) return go_acc(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
     if (cfg.dclass == 0) return go_range<6, 6>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
     if (cfg.dclass == 2) return go_range<6, 8>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
     return go_range<2, 8>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
@@ -1605,6 +2067,7 @@ hipError_t decode_query(const LaunchConfig &cfg, KernelQuery *q) {
     StreamArgs sa{};
     *q = KernelQuery{};
     if (cfg.pair) return go_pair(cfg, nullptr, fb, ip, sio, nullptr, q);
+    if (cfg.acc) return go_acc(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
     if (cfg.dclass == 0) return go_range<6, 6>(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
     if (cfg.dclass == 2) return go_range<6, 8>(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
     return go_range<2, 8>(cfg, nullptr, fb, ip, sio, sa, nullptr, q);

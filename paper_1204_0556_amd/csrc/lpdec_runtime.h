@@ -103,7 +103,24 @@ lpdec_status lpdec_fail(lpdec_status st, const char *fmt, ...);
 struct ScratchArena {
     char *base;    // device address, 256-byte aligned
     size_t bytes;  // capacity
+    // optional pinned host staging for per-frame metadata (scattered frames,
+    // completion flags); the caller keeps the previous call on this arena finished
+    // before the next one starts, so the staging is never overwritten in flight
+    char *host = nullptr;
+    size_t host_bytes = 0;
 };
+
+// Device scratch one decode launch needs: `fixed` bytes (queue counter and
+// per-frame metadata) plus `per_wg` bytes for each persistent workgroup; `grid`
+// is the grid the launch would use without a cap.  Each buffer is 256-byte
+// aligned, so an arena of fixed + per_wg * g + 1024 bytes holds g workgroups.
+struct ScratchNeed {
+    size_t fixed = 0, per_wg = 0, host = 0;
+    int grid = 0;
+    bool streamed = false;  // the streamed form (per-frame state): no arena serves it
+};
+lpdec_status lpdec_scratch_need(const lpdec_code *code, const lpdec_params *p, int nframes, bool scattered,
+                                ScratchNeed *out);
 
 // Decode core shared by every entry point (see lpdec_host.cpp).
 lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int nframes,

@@ -8,7 +8,11 @@
 //      while their footprint fits the budget: each frame reserves 4 n bytes of the
 //      device LLR arena (with a pinned staging twin), released when its request
 //      completes, and 4 n bytes of the pinned result arena, released when the
-//      caller collects the result;
+//      caller collects the result.  The budget covers the whole device footprint:
+//      each launch slot owns a fixed scratch region (queue counter, per-frame
+//      metadata, the persistent forms' per-workgroup buffers), sized at creation
+//      for the codes served and carved from the budget, and the LLR arena gets the
+//      rest, so the dispatcher never allocates device memory;
 //   3. launches: for every free launch slot (stream + workspace + flag arrays), the
 //      code whose admitted work is oldest gets a batch of up to max_batch_frames of
 //      its admitted frames: LLRs are copied into HBM on the slot's stream and one
@@ -96,7 +100,7 @@ struct Request {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
-    std::unique_ptr<Workspace> ws;
+    ScratchArena scratch{};  // this slot's device scratch (and pinned metadata staging)
     int *done = nullptr;       // pinned [cap]
     int32_t *iters = nullptr;  // pinned [cap]
     uint8_t *flags = nullptr;  // pinned [cap]
@@ -117,12 +121,15 @@ struct lpdec_server {
     bool gpu = true;
 
     float *d_llr = nullptr;  // device arena
+    char *d_scratch = nullptr;  // the launch slots' scratch regions (one allocation)
+    int64_t slot_scratch = 0;   // bytes of scratch per slot
     float *h_llr = nullptr;  // pinned staging arena
     float *h_x = nullptr;    // pinned result arena
     std::vector<float> null_llr, null_x;
     std::unique_ptr<RegionAllocator> regions;   // LLR arenas: the device budget
     std::unique_ptr<RegionAllocator> xregions;  // pinned result arena
     int64_t peak_bytes = 0;
+    int peak_launches = 0;  // launch slots busy at once, at most
 
     std::vector<Slot> slots;
     std::mutex mu;
@@ -277,7 +284,8 @@ bool lpdec_server::launch_into(Slot &s) {
     std::memset(s.done, 0, sizeof(int) * nf);
     const lpdec_code *code = codes[best];
     lpdec_status st = lpdec_decode_core(&code, 1, nf, nullptr, s.llr_off.data(), s.x_off.data(), d_llr, &params, h_x,
-                                        s.iters, s.flags, nullptr, nullptr, 0, s.stream, s.ws.get(), s.done);
+                                        s.iters, s.flags, nullptr, nullptr, 0, s.stream, nullptr, s.done,
+                                        &s.scratch);
     if (st != LPDEC_OK) thread_error = lpdec_last_error();
     hipError_t e = hipEventRecord(s.ev, s.stream);
     if (e != hipSuccess) thread_error = hipGetErrorString(e);
@@ -302,7 +310,12 @@ void lpdec_server::run() {
         for (Slot &s : slots)
             if (!s.busy && !launch_into(s)) break;
         bool busy = false;
-        for (Slot &s : slots) busy |= s.busy;
+        int nbusy = 0;
+        for (Slot &s : slots) {
+            busy |= s.busy;
+            nbusy += s.busy;
+        }
+        peak_launches = std::max(peak_launches, nbusy);
         if (stop && !busy) break;
         if (busy) {
             cv_work.wait_for(lk, std::chrono::microseconds(20));
@@ -361,7 +374,34 @@ lpdec_status lpdec_server_create(const lpdec_code *const *codes, const int32_t *
         }
         s->n.push_back(n);
     }
-    const int64_t cap = cfg.budget_bytes / (int64_t)sizeof(float);
+    // Launch-slot scratch: enough for a launch of max_batch_frames frames of any
+    // served code at its full persistent grid, but at most half the budget over all
+    // slots (a slot then runs fewer workgroups at once; results do not depend on
+    // the grid), and never less than one workgroup of the most demanding code.
+    int64_t need_full = 0, need_min = 0, host_meta = 0, nmin = INT64_MAX;
+    for (int c = 0; c < ncodes; ++c) nmin = std::min<int64_t>(nmin, s->n[c]);
+    if (gpu) {
+        for (int c = 0; c < ncodes; ++c) {
+            ScratchNeed sn;
+            lpdec_status st = lpdec_scratch_need(codes[c], &s->params, cfg.max_batch_frames, true, &sn);
+            if (st != LPDEC_OK) return st;
+            if (sn.streamed) return lpdec_fail(LPDEC_EUNSUPPORTED, "the server runs the persistent FP32 forms");
+            need_full = std::max<int64_t>(need_full, (int64_t)(sn.fixed + sn.per_wg * (size_t)sn.grid));
+            need_min = std::max<int64_t>(need_min, (int64_t)(sn.fixed + sn.per_wg));
+            host_meta = std::max<int64_t>(host_meta, (int64_t)sn.host);
+        }
+        const int64_t cap_share = cfg.budget_bytes / (2 * (int64_t)cfg.max_inflight);
+        int64_t per = std::min(need_full, std::max(need_min, cap_share));
+        per = (per + 255) / 256 * 256;
+        s->slot_scratch = per;
+    }
+    const int64_t scratch_total = s->slot_scratch * cfg.max_inflight;
+    if (cfg.budget_bytes - scratch_total < (int64_t)sizeof(float) * nmin)
+        return lpdec_fail(LPDEC_EINVAL,
+                          "budget of %lld bytes is too small: the launch slots' scratch takes %lld bytes and one "
+                          "frame of the shortest code needs %lld more",
+                          (long long)cfg.budget_bytes, (long long)scratch_total, (long long)(sizeof(float) * nmin));
+    const int64_t cap = (cfg.budget_bytes - scratch_total) / (int64_t)sizeof(float);
     s->regions.reset(new RegionAllocator(cap));
     s->xregions.reset(new RegionAllocator(cap));
     s->admitted.resize(ncodes);
@@ -370,7 +410,10 @@ lpdec_status lpdec_server_create(const lpdec_code *const *codes, const int32_t *
     if (gpu) {
         hipError_t e;
         if ((e = hipMalloc(&s->d_llr, sizeof(float) * cap)) != hipSuccess)
-            return lpdec_fail(LPDEC_ENOMEM, "device arena of %lld bytes: %s", (long long)cfg.budget_bytes,
+            return lpdec_fail(LPDEC_ENOMEM, "device arena of %lld bytes: %s", (long long)(sizeof(float) * cap),
+                              hipGetErrorString(e));
+        if ((e = hipMalloc(reinterpret_cast<void **>(&s->d_scratch), (size_t)scratch_total)) != hipSuccess)
+            return lpdec_fail(LPDEC_ENOMEM, "launch scratch of %lld bytes: %s", (long long)scratch_total,
                               hipGetErrorString(e));
         const unsigned fl = hipHostMallocMapped | hipHostMallocCoherent;
         if ((e = hipHostMalloc(reinterpret_cast<void **>(&s->h_llr), sizeof(float) * cap, hipHostMallocDefault)) !=
@@ -382,9 +425,13 @@ lpdec_status lpdec_server_create(const lpdec_code *const *codes, const int32_t *
                 (e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming)) != hipSuccess ||
                 (e = hipHostMalloc(reinterpret_cast<void **>(&sl.done), sizeof(int) * ncap, fl)) != hipSuccess ||
                 (e = hipHostMalloc(reinterpret_cast<void **>(&sl.iters), sizeof(int32_t) * ncap, fl)) != hipSuccess ||
-                (e = hipHostMalloc(reinterpret_cast<void **>(&sl.flags), ncap, fl)) != hipSuccess)
+                (e = hipHostMalloc(reinterpret_cast<void **>(&sl.flags), ncap, fl)) != hipSuccess ||
+                (e = hipHostMalloc(reinterpret_cast<void **>(&sl.scratch.host), (size_t)host_meta,
+                                   hipHostMallocDefault)) != hipSuccess)
                 return lpdec_fail(LPDEC_EDEVICE, "launch slot set-up: %s", hipGetErrorString(e));
-            sl.ws.reset(new Workspace());
+            sl.scratch.base = s->d_scratch + (&sl - s->slots.data()) * s->slot_scratch;
+            sl.scratch.bytes = (size_t)s->slot_scratch;
+            sl.scratch.host_bytes = (size_t)host_meta;
         }
     } else {
         s->null_llr.assign(cap, 0.0f);
@@ -416,10 +463,13 @@ lpdec_status lpdec_server_submit(lpdec_server *s, int32_t code, int32_t frames, 
     r->iters.assign(frames, 0);
     r->flags.assign(frames, 0);
     std::lock_guard<std::mutex> lk(s->mu);
-    if (bytes > s->cfg.budget_bytes) {
+    const int64_t arena = s->regions->capacity() * (int64_t)sizeof(float);
+    if (bytes > arena) {
         ++s->rejected;
-        return lpdec_fail(LPDEC_EINVAL, "request of %lld bytes exceeds the server budget of %lld bytes",
-                          (long long)bytes, (long long)s->cfg.budget_bytes);
+        return lpdec_fail(LPDEC_EINVAL,
+                          "request of %lld bytes exceeds the server budget of %lld bytes (%lld bytes of LLR arena "
+                          "beside the launch slots' scratch)",
+                          (long long)bytes, (long long)s->cfg.budget_bytes, (long long)arena);
     }
     if ((int)s->queue.size() >= s->cfg.max_pending) {
         ++s->rejected;
@@ -505,6 +555,9 @@ lpdec_status lpdec_server_get_stats(lpdec_server *s, lpdec_server_stats *st) {
     st->bits_completed = s->bits_done;
     st->inflight_bytes = s->regions->used() * (int64_t)sizeof(float);
     st->peak_bytes = s->peak_bytes;
+    st->workspace_bytes = s->slot_scratch * (int64_t)s->slots.size();
+    st->peak_device_bytes = st->workspace_bytes + s->peak_bytes;
+    st->peak_concurrent_launches = s->peak_launches;
     st->launches = s->launches;
     st->queued = (int32_t)s->queue.size();
     int running = 0;
@@ -537,8 +590,8 @@ void lpdec_server_destroy(lpdec_server *s) {
     for (Slot &sl : s->slots) {
         if (s->gpu) {
             if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-            sl.ws.reset();
             if (sl.stream) (void)hipStreamDestroy(sl.stream);
+            if (sl.scratch.host) (void)hipHostFree(sl.scratch.host);
             if (sl.ev) (void)hipEventDestroy(sl.ev);
             if (sl.done) (void)hipHostFree(sl.done);
             if (sl.iters) (void)hipHostFree(sl.iters);
@@ -550,6 +603,7 @@ void lpdec_server_destroy(lpdec_server *s) {
         }
     }
     if (s->d_llr) (void)hipFree(s->d_llr);
+    if (s->d_scratch) (void)hipFree(s->d_scratch);
     if (s->h_llr) (void)hipHostFree(s->h_llr);
     if (s->h_x) (void)hipHostFree(s->h_x);
     delete s;

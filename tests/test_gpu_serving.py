@@ -46,7 +46,11 @@ def test_results_same_alone_and_in_the_mix():
     mixed = [srv.wait(t, timeout=60.0) for t in tickets]
     st = srv.stats()
     srv.close()
-    assert st["completed"] == len(trace) and st["peak_bytes"] <= 64 << 20
+    print(f"stats: {st}", flush=True)
+    assert st["completed"] == len(trace) and st["peak_device_bytes"] <= 64 << 20
+    assert st["workspace_bytes"] > 0 and st["peak_device_bytes"] == st["workspace_bytes"] + st["peak_bytes"]
+    # requests submitted together ran in launches that overlapped on the device
+    assert st["peak_concurrent_launches"] > 1
     # each request alone, in a fresh server, and through the plain batch API
     for k in range(0, len(trace), max(1, len(trace) // 6)):
         r = trace[k]
@@ -63,13 +67,46 @@ def test_results_same_alone_and_in_the_mix():
 def test_small_budget_queues_without_exceeding_it():
     Hs, codes = _codes()
     H = Hs[2]
-    budget = 4 * H.n * 40  # forty n=2640 frames
-    srv = lp.Server(codes, budget_bytes=budget, max_batch_frames=64, max_inflight=2)
+    # resident codes only: the launch slots' scratch is a few KB; the LLR arena then
+    # holds about forty n=2640 frames, so twelve requests of sixteen frames queue
+    budget = 4 * H.n * 40 + (16 << 10)
+    srv = lp.Server([codes[0], codes[2]], budget_bytes=budget, max_batch_frames=64, max_inflight=2)
     llr = W.awgn_batch(H, 16, 2.5, tag="budget")
-    tickets = [srv.submit(2, llr) for _ in range(12)]
+    tickets = [srv.submit(1, llr) for _ in range(12)]
     outs = [srv.wait(t, timeout=60.0) for t in tickets]
     st = srv.stats()
     srv.close()
-    assert st["completed"] == 12 and 0 < st["peak_bytes"] <= budget
+    print(f"stats: {st}", flush=True)
+    assert st["completed"] == 12 and 0 < st["peak_bytes"] <= budget - st["workspace_bytes"]
+    assert st["peak_device_bytes"] <= budget
     for o in outs[1:]:
         assert np.array_equal(o[0], outs[0][0])
+
+
+def test_large_code_requests_stay_within_the_device_budget():
+    """n = 16384 requests (persistent-global form: each workgroup holds about 0.5 MB of
+    state) through a 96 MB budget: the server's device allocations, measured from the
+    device's free memory, stay within the budget, the dispatcher allocates nothing
+    while serving, and the results equal a plain decode of the same frames."""
+    H = W.gallager36(16384)
+    code = lp.Code(H)
+    llr = W.awgn_batch(H, 64, 2.5, tag="budget-large")
+    ref = _alone(code, llr)  # also loads the kernels before memory is measured
+    budget = 96 << 20
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    srv = lp.Server([code], budget_bytes=budget, max_batch_frames=256, max_inflight=4)
+    free1 = torch.cuda.mem_get_info()[0]
+    tickets = [srv.submit(0, llr[8 * k:8 * (k + 1)]) for k in range(8)]
+    outs = [srv.wait(t, timeout=120.0) for t in tickets]
+    free2 = torch.cuda.mem_get_info()[0]
+    st = srv.stats()
+    srv.close()
+    print(f"server device bytes {free0 - free1}, during serving {free1 - free2}; stats {st}", flush=True)
+    assert free0 - free1 <= budget + (8 << 20)  # allocation granularity
+    assert abs(free1 - free2) <= (2 << 20)
+    assert st["peak_device_bytes"] <= budget and st["workspace_bytes"] > 0
+    x = np.concatenate([o[0] for o in outs])
+    it = np.concatenate([o[1] for o in outs])
+    fl = np.concatenate([o[2] for o in outs])
+    assert np.array_equal(x, ref[0]) and np.array_equal(it, ref[1]) and np.array_equal(fl, ref[2])

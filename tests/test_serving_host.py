@@ -30,6 +30,9 @@ def test_requests_complete_and_stats_add_up():
     assert st["bits_completed"] == total_bits
     assert 0.0 <= st["p50_latency_s"] <= st["p99_latency_s"] <= st["max_latency_s"]
     assert st["inflight_bytes"] == 0
+    # the host-only executor has no launch scratch: the device footprint is the arena's
+    assert st["workspace_bytes"] == 0 and st["peak_device_bytes"] == st["peak_bytes"]
+    assert st["peak_concurrent_launches"] >= 1
     s.close()
 
 
