@@ -171,9 +171,13 @@ def workload_uneven(args, lp, W, torch):
     batch = W.mixed_batch(codes_h, 16384, 1.5, 3.0, tag="uneven")
     flat, off = batch.flat_llr()
     codes = [lp.Code(H) for H in codes_h]
-    resident = all(c.info["resident_capable"] for c in codes)
     dev_llr = torch.from_numpy(flat).cuda()
-    P = W.PAPER_PARAMS
+    # the fused launch's form, workgroups per CU and frame order, picked by the
+    # library's multi-code autotuner on this batch
+    (mode, bpc, order), tune_ms = lp.autotune_multi(codes, batch.code_of_frame, off, dev_llr,
+                                                    max_blocks_per_cu=2, **W.PAPER_PARAMS)
+    resident = mode == lp.MODE_RESIDENT
+    P = dict(W.PAPER_PARAMS, mode=mode)
 
     def step():
         return lp.decode_multi(codes, batch.code_of_frame, off, dev_llr, off, flat.size, **P)
@@ -202,6 +206,11 @@ def workload_uneven(args, lp, W, torch):
                                "{576,1152,2304,4608,6912,8064} (variable degrees {2,3,6}, check degrees "
                                "{6,7,8}), Eb/N0 U[1.5,3] dB per frame, one persistent launch", "frames": 16384},
         "mean_iterations": round(float(it.mean()), 2),
+        "autotune": {"mode": {lp.MODE_RESIDENT: "resident", lp.MODE_PERSISTENT_GLOBAL: "persistent_global"}[mode],
+                     "blocks_per_cu": bpc, "order": "larger codes first" if order == 1 else "submission order",
+                     "candidates_ms": {f"{'resident' if m == lp.MODE_RESIDENT else 'persistent_global'}/"
+                                       f"{'larger-first' if o == 1 else 'submission'}/{b}": round(v, 3)
+                                       for (m, o, b), v in tune_ms.items()}},
         # every code of the batch fits the register-resident form (check degrees
         # 6..8): the state stays on chip, so the roof is VALU issue
         "roofline": ({"bound": "alu", "achieved": round(achieved / 1e3, 3), "peak": VALU_PEAK_GOPS / 1e3,

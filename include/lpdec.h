@@ -303,6 +303,27 @@ lpdec_status lpdec_code_set_tuning(lpdec_code *code, int32_t mode, int32_t block
 lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, const lpdec_params *p,
                             int32_t max_blocks_per_cu, int32_t *best_out, float *ms_out, void *stream);
 
+/* Autotuner for lpdec_decode_multi: decode the caller's sample set (laid out as for
+ * lpdec_decode_multi, x written at the LLR offsets into a scratch buffer) once per
+ * candidate of the fused persistent launch -- the form (RESIDENT when every code
+ * fits it, PERSISTENT_GLOBAL) x workgroups per CU 1..max_blocks_per_cu x the order
+ * frames are handed out (1: frames of larger codes first, 0: submission order) --
+ * after one untimed warm-up per form and order, timing each with HIP events on
+ * `stream`; the fastest becomes the tuning of the set's leading code codes[0]
+ * (workgroups per CU of that form and the frame order; multi-code launches take
+ * their tuning from codes[0]).  p must ask for mode AUTO and FP32 storage; later
+ * decodes pass mode = best_out[0].  Results do not depend on any of these choices.
+ *   best_out  host [3], may be NULL: {mode, blocks_per_cu, order}
+ *   ms_out    host [4*max_blocks_per_cu], may be NULL: time of (form f, order o,
+ *             blocks b) at [(2 f + o) * max_blocks_per_cu + b - 1], f = 0 resident,
+ *             1 persistent-global; -1 where not run
+ * Synchronous; scratch outputs are allocated and freed inside the call. */
+lpdec_status lpdec_autotune_multi(const lpdec_code *const *codes, int32_t ncodes, int32_t nframes,
+                                  const int32_t *code_of_frame, const int64_t *llr_offset,
+                                  const float *llr, int64_t llr_len, const lpdec_params *p,
+                                  int32_t max_blocks_per_cu, int32_t *best_out, float *ms_out,
+                                  void *stream);
+
 /* The check-node operation alone: z_k = Pi_PPd(v_k) for `count` vectors of
  * degree d (2 <= d <= LPDEC_MAX_CHECK_DEGREE), Algorithm 2 / Sec. 4.4.
  *   v, z  device [count*d] FP32, row-major (z may not alias v).  Entries of v

@@ -17,7 +17,7 @@ import os
 import numpy as np
 
 __all__ = [
-    "Code", "decode", "decode_noalloc", "decode_state", "decode_multi", "project", "default_params", "last_error",
+    "Code", "decode", "decode_noalloc", "decode_state", "decode_multi", "autotune_multi", "project", "default_params", "last_error",
     "LpdecError", "FLAG_CONVERGED", "FLAG_INTEGRAL", "FLAG_CODEWORD", "FLAG_CERTIFIED", "FLAG_INVALID",
     "MODE_AUTO", "MODE_RESIDENT", "MODE_STREAMED", "MODE_PERSISTENT_GLOBAL", "STORAGE_FP32", "STORAGE_FP16",
     "MAX_CHECK_DEGREE", "library_path", "Server", "EXECUTOR_GPU", "EXECUTOR_HOST_NULL",
@@ -114,6 +114,9 @@ def _load():
     lib.lpdec_code_set_tuning.restype = ctypes.c_int
     lib.lpdec_autotune.argtypes = [vp, i32, vp, P(_Params), i32, P(i32), P(ctypes.c_float), vp]
     lib.lpdec_autotune.restype = ctypes.c_int
+    lib.lpdec_autotune_multi.argtypes = [P(vp), i32, i32, P(i32), P(i64), vp, i64, P(_Params), i32, P(i32),
+                                         P(ctypes.c_float), vp]
+    lib.lpdec_autotune_multi.restype = ctypes.c_int
     lib.lpdec_decode_dual.argtypes = [vp, i32, vp, P(_Params), vp, vp, vp, vp]
     lib.lpdec_decode_dual.restype = ctypes.c_int
     lib.lpdec_evaluate.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -408,6 +411,32 @@ def decode_multi(codes, code_of_frame, llr_offset, llr, x_offset, x_len, stream=
                                    _dev_ptr(it, torch.int32, "iters"), _dev_ptr(fl, torch.uint8, "flags"),
                                    _stream(stream)))
     return x, it, fl
+
+
+def autotune_multi(codes, code_of_frame, llr_offset, llr, max_blocks_per_cu=2, stream=None, **params):
+    """Time decode_multi launches of this frame set over the fused launch's candidates
+    (form x workgroups per CU x frame order) and keep the fastest as the tuning of
+    codes[0].  Returns ((mode, blocks_per_cu, order), {(mode, order, blocks): ms})."""
+    torch = _torch()
+    cof = np.ascontiguousarray(code_of_frame, dtype=np.int32)
+    lo = np.ascontiguousarray(llr_offset, dtype=np.int64)
+    handles = (ctypes.c_void_p * len(codes))(*[c.handle.value for c in codes])
+    mb = int(max_blocks_per_cu)
+    best = (ctypes.c_int32 * 3)()
+    ms = (ctypes.c_float * (4 * mb))()
+    p = _params(**params)
+    P = ctypes.POINTER
+    _check(_lib.lpdec_autotune_multi(handles, len(codes), int(cof.size), cof.ctypes.data_as(P(ctypes.c_int32)),
+                                     lo.ctypes.data_as(P(ctypes.c_int64)), _dev_ptr(llr, torch.float32, "llr"),
+                                     int(llr.numel()), ctypes.byref(p), mb, best, ms, _stream(stream)))
+    times = {}
+    for f, mode in enumerate((MODE_RESIDENT, MODE_PERSISTENT_GLOBAL)):
+        for o in range(2):
+            for b in range(mb):
+                v = ms[(2 * f + o) * mb + b]
+                if v >= 0:
+                    times[(mode, o, b + 1)] = float(v)
+    return (best[0], best[1], best[2]), times
 
 
 def project(v, stream=None):

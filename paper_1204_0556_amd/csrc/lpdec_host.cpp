@@ -662,7 +662,7 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
         // lookup costs a dependent load per frame, so equal-size codes skip it
         bool mixed_sizes = false;
         for (int c = 1; c < ncodes; ++c) mixed_sizes = mixed_sizes || codes[c]->dc.E != codes[0]->dc.E;
-        const bool ordered = mixed_sizes && code_of_frame &&
+        const bool ordered = mixed_sizes && code_of_frame && codes[0]->tune_order != 0 &&
                              (cfg.form == Form::Resident || cfg.form == Form::PersistentGlobal);
         const size_t bytes = tbl_bytes + (size_t)nframes * (2 * sizeof(int64_t) + sizeof(int32_t)) +
                              (ordered ? (size_t)nframes * sizeof(int32_t) : 0);
@@ -1099,6 +1099,100 @@ lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, c
     if (best_out) {
         best_out[0] = best;
         best_out[1] = best_var;
+    }
+    return LPDEC_OK;
+}
+
+lpdec_status lpdec_autotune_multi(const lpdec_code *const *codes, int32_t ncodes, int32_t nframes,
+                                  const int32_t *code_of_frame, const int64_t *llr_offset, const float *llr,
+                                  int64_t llr_len, const lpdec_params *pin, int32_t max_bpc, int32_t *best_out,
+                                  float *ms_out, void *stream_v) {
+    if (!codes || ncodes < 1 || !code_of_frame || !llr_offset || !llr)
+        return fail(LPDEC_EINVAL, "codes, code_of_frame, llr_offset and llr must not be NULL");
+    for (int c = 0; c < ncodes; ++c)
+        if (!codes[c]) return fail(LPDEC_EINVAL, "codes[%d] is NULL", c);
+    if (nframes < 1) return fail(LPDEC_EINVAL, "nframes must be >= 1");
+    if (max_bpc < 1 || max_bpc > 32) return fail(LPDEC_EINVAL, "max_blocks_per_cu must lie in 1..32");
+    lpdec_params p = pin ? *pin : lpdec_default_params();
+    lpdec_status st = check_params(&p);
+    if (st != LPDEC_OK) return st;
+    if (p.mode != LPDEC_MODE_AUTO || p.storage != LPDEC_STORAGE_FP32)
+        return fail(LPDEC_EINVAL, "the multi-code tuner picks the form: pass mode AUTO and FP32 storage");
+    for (int f = 0; f < nframes; ++f) {
+        const int c = code_of_frame[f];
+        if (c < 0 || c >= ncodes) return fail(LPDEC_EINVAL, "frame %d: code index %d out of range", f, c);
+        if (llr_offset[f] < 0 || llr_offset[f] + codes[c]->dc.n > llr_len)
+            return fail(LPDEC_EINVAL, "frame %d: llr range outside llr_len %lld", f, (long long)llr_len);
+    }
+    lpdec_code *lead = const_cast<lpdec_code *>(codes[0]);
+    const Shape s = shape_of(codes, ncodes);
+    LaunchConfig probe{};
+    const bool res_ok = resident_config(s, &probe);
+    const int forms[2] = {LPDEC_MODE_RESIDENT, LPDEC_MODE_PERSISTENT_GLOBAL};
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    if (ms_out)
+        for (int k = 0; k < 4 * max_bpc; ++k) ms_out[k] = -1.0f;
+    const int saved_bpc[2] = {lead->tune_bpc[0], lead->tune_bpc[1]}, saved_order = lead->tune_order;
+    float *x = nullptr;
+    int32_t *it = nullptr;
+    uint8_t *fl = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best[3] = {0, 0, -1};
+    float best_ms = 0.0f;
+    auto run = [&]() -> lpdec_status {
+        HIP_TRY(hipMalloc(&x, sizeof(float) * (size_t)llr_len));
+        HIP_TRY(hipMalloc(&it, sizeof(int32_t) * nframes));
+        HIP_TRY(hipMalloc(&fl, nframes));
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        for (int fi = 0; fi < 2; ++fi) {
+            if (forms[fi] == LPDEC_MODE_RESIDENT && !res_ok) continue;
+            const int form = form_of_mode(forms[fi]);
+            lpdec_params q = p;
+            q.mode = forms[fi];
+            for (int order = 0; order < 2; ++order) {
+                lead->tune_order = order;
+                for (int b = 0; b <= max_bpc; ++b) {
+                    lead->tune_bpc[form] = b == 0 ? 1 : b;  // b = 0: untimed warm-up
+                    HIP_TRY(hipEventRecord(e0, stream));
+                    lpdec_status r = lpdec_decode_core(codes, ncodes, nframes, code_of_frame, llr_offset, llr_offset,
+                                                       llr, &q, x, it, fl, nullptr, nullptr, 0, stream, nullptr,
+                                                       nullptr);
+                    if (r != LPDEC_OK) return r;
+                    HIP_TRY(hipEventRecord(e1, stream));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float ms = 0.0f;
+                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    if (b == 0) continue;
+                    if (ms_out) ms_out[(fi * 2 + order) * max_bpc + b - 1] = ms;
+                    if (best[2] < 0 || ms < best_ms) {
+                        best[0] = forms[fi];
+                        best[1] = b;
+                        best[2] = order;
+                        best_ms = ms;
+                    }
+                }
+                lead->tune_bpc[form] = saved_bpc[fi];
+            }
+        }
+        return LPDEC_OK;
+    };
+    st = run();
+    if (x) (void)hipFree(x);
+    if (it) (void)hipFree(it);
+    if (fl) (void)hipFree(fl);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    lead->tune_bpc[0] = saved_bpc[0];
+    lead->tune_bpc[1] = saved_bpc[1];
+    lead->tune_order = saved_order;
+    if (st != LPDEC_OK) return st;
+    lead->tune_bpc[form_of_mode(best[0])] = best[1];
+    lead->tune_order = best[2];
+    if (best_out) {
+        best_out[0] = best[0];
+        best_out[1] = best[1];
+        best_out[2] = best[2];
     }
     return LPDEC_OK;
 }

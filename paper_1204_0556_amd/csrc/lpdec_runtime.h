@@ -85,6 +85,9 @@ struct lpdec_code {
     lpdec::LaunchConfig resident_cfg{};
     int tune_bpc[3] = {0, 0, 0};     // workgroups per CU by form (0: runtime estimate)
     int tune_variant[3] = {-1, -1, -1};  // kernel variant by form (streamed only; -1: default)
+    // multi-code launches led by this code: hand out frames of larger codes first
+    // (1), in submission order (0), or the default (-1: larger first when sizes differ)
+    int tune_order = -1;
     Workspace ws;
     ~lpdec_code() {
         if (d_dc) (void)hipFree(d_dc);

@@ -105,6 +105,13 @@ def test_multi_argument_checks(lib):
                                   ctypes.c_int64(0), None, None, None) == EINVAL
 
 
+def test_multi_autotune_argument_checks(lib):
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.lpdec_autotune_multi.argtypes = [vp, i32, i32, vp, vp, vp, i64, vp, i32, vp, vp, vp]
+    assert lib.lpdec_autotune_multi(None, 1, 4, None, None, None, 0, None, 2, None, None, None) == EINVAL
+    assert "NULL" in lib.lpdec_last_error().decode()
+
+
 def test_tuning_argument_checks(lib):
     vp, i32 = ctypes.c_void_p, ctypes.c_int32
     lib.lpdec_code_set_tuning.argtypes = [vp, i32, i32, i32]

@@ -76,3 +76,26 @@ def test_tuning_rejects_bad_values():
     with pytest.raises(lp.LpdecError):
         code.set_tuning(lp.MODE_STREAMED, 1, 3)
     code.set_tuning(lp.MODE_STREAMED, 1, 2)  # n = 96: staging allowed, default already
+
+
+def test_multi_autotune_keeps_results_and_records_choice():
+    codes_h = [W.irregular_half(n) for n in (576, 2304, 8064)]
+    batch = W.mixed_batch(codes_h, 512, 1.5, 3.0, tag="tune-multi")
+    flat, off = batch.flat_llr()
+    codes = [lp.Code(H) for H in codes_h]
+    llr = torch.from_numpy(flat).cuda()
+    kw = dict(W.PAPER_PARAMS, max_iter=200)
+
+    def run(**extra):
+        x, it, fl = lp.decode_multi(codes, batch.code_of_frame, off, llr, off, flat.size, **kw, **extra)
+        torch.cuda.synchronize()
+        return x.cpu().numpy(), it.cpu().numpy(), fl.cpu().numpy()
+
+    ref = run()
+    (mode, bpc, order), times = lp.autotune_multi(codes, batch.code_of_frame, off, llr, max_blocks_per_cu=2, **kw)
+    print(f"multi-code tuning: mode {mode} blocks {bpc} order {order}; {times}", flush=True)
+    assert mode in (lp.MODE_RESIDENT, lp.MODE_PERSISTENT_GLOBAL) and 1 <= bpc <= 2 and order in (0, 1)
+    # every code fits the resident form: both forms, both orders, two grids were timed
+    assert len(times) == 8 and all(v > 0 for v in times.values())
+    for a, b in zip(ref, run(mode=mode)):
+        assert np.array_equal(a, b)
