@@ -288,6 +288,18 @@ lpdec_status lpdec_code_launch_info(const lpdec_code *code, const lpdec_params *
 lpdec_status lpdec_code_set_tuning(lpdec_code *code, int32_t mode, int32_t blocks_per_cu,
                                    int32_t variant);
 
+/* Streamed form: issue each block of 16 iteration launches as one replay of a
+ * captured HIP graph (enable = 1) instead of 16 kernel launches (enable = 0, the
+ * default).  The graph holds kernel nodes only -- the decode launch and a
+ * one-thread kernel that advances the launch index the decode reads from device
+ * memory -- and is captured and instantiated on first use for a set of launch
+ * arguments, then cached with the code's workspace and replayed while the
+ * arguments (buffers, batch, parameters, launch shape) stay the same.  A replay may
+ * run launches past max_iter, which find every frame finished and do nothing.
+ * Results are the same either way.  Not synchronised with decodes on other
+ * threads. */
+lpdec_status lpdec_code_set_graph(lpdec_code *code, int32_t enable);
+
 /* Autotuner: decode the caller's sample batch (device llr [batch*n]) with
  * parameters `p` once per candidate launch -- workgroups per CU 1..max_blocks_per_cu,
  * times the variants the code allows (streamed form: 0, 1, 2; resident form: 0, 1

@@ -112,6 +112,8 @@ def _load():
     lib.lpdec_code_launch_info.restype = ctypes.c_int
     lib.lpdec_code_set_tuning.argtypes = [vp, i32, i32, i32]
     lib.lpdec_code_set_tuning.restype = ctypes.c_int
+    lib.lpdec_code_set_graph.argtypes = [vp, i32]
+    lib.lpdec_code_set_graph.restype = ctypes.c_int
     lib.lpdec_autotune.argtypes = [vp, i32, vp, P(_Params), i32, P(i32), P(ctypes.c_float), vp]
     lib.lpdec_autotune.restype = ctypes.c_int
     lib.lpdec_autotune_multi.argtypes = [P(vp), i32, i32, P(i32), P(i64), vp, i64, P(_Params), i32, P(i32),
@@ -232,6 +234,10 @@ class Code:
 
     def set_tuning(self, mode: int, blocks_per_cu: int = 0, variant: int = -1):
         _check(_lib.lpdec_code_set_tuning(self.handle, int(mode), int(blocks_per_cu), int(variant)))
+
+    def set_graph(self, enable: bool):
+        """Streamed form: replay blocks of iteration launches from a captured graph."""
+        _check(_lib.lpdec_code_set_graph(self.handle, 1 if enable else 0))
 
     def autotune(self, llr, max_blocks_per_cu: int = 4, stream=None, **params):
         """Time decodes of the sample batch llr (float32 [B, n] CUDA tensor) over the

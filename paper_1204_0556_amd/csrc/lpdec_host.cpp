@@ -829,19 +829,79 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
         // Iterations are issued in blocks; after each block the number of frames
         // still running is copied to pinned memory and checked one block later.
         const int block = 16;
+        // Graph replay: a block is one launch of a graph captured once per set of
+        // launch arguments (kernel nodes only: the decode and a one-thread kernel that
+        // advances the launch index in device memory).  A replay may run launches past
+        // max_iter; they find every frame finished and do nothing.
+        const bool graph = c0->graph;
+        if (graph) {
+            HIP_TRY(ws.launch_dev.ensure(sizeof(int)));
+            sa.launch_dev = static_cast<int *>(ws.launch_dev.p);
+            HIP_TRY(launch_fill_i32(static_cast<int *>(ws.launch_dev.p), 0, 1, stream));
+            struct Key {
+                LaunchConfig cfg;
+                const DevCode *codes;
+                FrameBatch fb;
+                IterParams ip;
+                StateIO sio;
+                StreamArgs sa;
+            } key;
+            std::memset(&key, 0, sizeof key);
+            key.cfg = cfg;
+            key.codes = codes_dev;
+            key.fb = fb;
+            key.ip = ip;
+            key.sio = sio;
+            key.sa = sa;
+            const char *kb = reinterpret_cast<const char *>(&key);
+            if (!ws.graph || ws.graph_key.size() != sizeof key ||
+                std::memcmp(ws.graph_key.data(), kb, sizeof key) != 0) {
+                if (ws.graph) HIP_TRY(hipGraphExecDestroy(ws.graph));
+                ws.graph = nullptr;
+                if (!ws.capture) HIP_TRY(hipStreamCreateWithFlags(&ws.capture, hipStreamNonBlocking));
+                HIP_TRY(hipStreamBeginCapture(ws.capture, hipStreamCaptureModeThreadLocal));
+                hipError_t ce = hipSuccess;
+                for (int k = 0; k < block && ce == hipSuccess; ++k) {
+                    ce = launch_decode(cfg, codes_dev, fb, ip, sio, sa, ws.capture);
+                    if (ce == hipSuccess) ce = launch_advance(static_cast<int *>(ws.launch_dev.p), ws.capture);
+                }
+                hipGraph_t g = nullptr;
+                const hipError_t ee = hipStreamEndCapture(ws.capture, &g);
+                if (ce != hipSuccess || ee != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return fail(LPDEC_EDEVICE, "capturing the iteration block failed: %s",
+                                hipGetErrorString(ce != hipSuccess ? ce : ee));
+                }
+                const hipError_t ie = hipGraphInstantiate(&ws.graph, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (ie != hipSuccess) {
+                    ws.graph = nullptr;
+                    return fail(LPDEC_EDEVICE, "instantiating the iteration block failed: %s", hipGetErrorString(ie));
+                }
+                ws.graph_key.assign(kb, kb + sizeof key);
+            }
+        }
         hipEvent_t ev[2] = {nullptr, nullptr};
         HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
         int issued = 0, blk = 0;
         lpdec_status rs = LPDEC_OK;
         while (issued < p.max_iter) {
-            const int cnt = std::min(block, p.max_iter - issued);
-            for (int k = 0; k < cnt; ++k) {
-                ip.launch = issued + k;
-                hipError_t e = launch_decode(cfg, codes_dev, fb, ip, sio, sa, stream);
+            const int cnt = graph ? block : std::min(block, p.max_iter - issued);
+            if (graph) {
+                const hipError_t e = hipGraphLaunch(ws.graph, stream);
                 if (e != hipSuccess) {
-                    rs = fail(LPDEC_EDEVICE, "streamed launch failed: %s", hipGetErrorString(e));
+                    rs = fail(LPDEC_EDEVICE, "graph launch failed: %s", hipGetErrorString(e));
                     break;
+                }
+            } else {
+                for (int k = 0; k < cnt; ++k) {
+                    ip.launch = issued + k;
+                    hipError_t e = launch_decode(cfg, codes_dev, fb, ip, sio, sa, stream);
+                    if (e != hipSuccess) {
+                        rs = fail(LPDEC_EDEVICE, "streamed launch failed: %s", hipGetErrorString(e));
+                        break;
+                    }
                 }
             }
             if (rs != LPDEC_OK) break;
@@ -1100,6 +1160,13 @@ lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, c
         best_out[0] = best;
         best_out[1] = best_var;
     }
+    return LPDEC_OK;
+}
+
+lpdec_status lpdec_code_set_graph(lpdec_code *code, int32_t enable) {
+    if (!code) return fail(LPDEC_EINVAL, "code must not be NULL");
+    if (enable != 0 && enable != 1) return fail(LPDEC_EINVAL, "enable must be 0 or 1 (got %d)", enable);
+    code->graph = enable != 0;
     return LPDEC_OK;
 }
 

@@ -109,6 +109,9 @@ struct StreamArgs {
     float *gmu;             // gamma/mu in internal variable order: [workgroups or frames][gmu_stride]
     unsigned *gxprev;       // accumulator mode, persistent form: previous x bits [workgroups][gmu_stride]
     int gmu_stride;
+    // streamed form replayed from a captured graph: the launch index lives here
+    // (advanced by a one-thread kernel after each launch) instead of in IterParams
+    const int *launch_dev;
 };
 
 // Launchers (defined in lpdec_kernels.hip).  Return hipSuccess or the launch error.
@@ -158,5 +161,6 @@ hipError_t launch_stream_export(const DevCode *codes_dev, int nframes, int E_int
                                 const StreamArgs &sa, hipStream_t stream);
 hipError_t launch_project(int d, int count, const float *v, float *z, hipStream_t stream);
 hipError_t launch_fill_i32(int *p, int value, int count, hipStream_t stream);
+hipError_t launch_advance(int *p, hipStream_t stream);  // *p += 1 (one thread)
 
 }  // namespace lpdec

@@ -191,6 +191,22 @@ hipError_t launch_fill_i32(int *p, int value, int count, hipStream_t stream) {
     return hipGetLastError();
 }
 
+__global__ void k_advance(int *p) {
+    if (threadIdx.x == 0) *p += 1;
+}
+
+hipError_t launch_advance(int *p, hipStream_t stream) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, stream, p);
+    return hipGetLastError();
+}
+
+// Streamed form: iterations every unfinished frame has run before this launch --
+// from the launch's arguments, or from device memory when the launches are
+// replayed from a captured graph (whose arguments are fixed).
+__device__ __forceinline__ int streamed_launch(const IterParams &ip, const StreamArgs &sa) {
+    return sa.launch_dev ? __builtin_amdgcn_readfirstlane(*as_global(sa.launch_dev)) : ip.launch;
+}
+
 // ---------------------------------------------------------------------------
 // Workgroup helpers.
 
@@ -485,8 +501,9 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             smask = __ballot(act);
         }
     };
+    const int launch = PERSIST ? 0 : streamed_launch(ip, sa);
     if constexpr (!PERSIST) {
-        if (blockIdx.x == 0 && tid == 0) sa.active_count[(ip.launch + 1) & 1] = 0;  // next launch's counter
+        if (blockIdx.x == 0 && tid == 0) sa.active_count[(launch + 1) & 1] = 0;  // next launch's counter
     }
     // STG: start the direct-to-LDS copy of frame g's z, u (16 bytes per lane) and
     // gamma/mu (4 bytes per lane); each wave copies every NW-th 1 KB block
@@ -545,7 +562,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         float *gmu_row = sa.gmu ? sa.gmu + (size_t)(PERSIST ? blockIdx.x : f) * sa.gmu_stride : nullptr;
 
         // streamed form: unfinished frames advance in lockstep, one iteration per launch
-        const int iter0 = PERSIST ? 0 : ip.launch;
+        const int iter0 = launch;
 
         // -- per-code register metadata -------------------------------------
         if constexpr (CPT > 0) {
@@ -995,7 +1012,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             if (tid == 0) {
                 sa.st[f].iter = it;
                 if (fin) sa.st[f].done = 1;
-                else atomicAdd(sa.active_count + (ip.launch & 1), 1);
+                else atomicAdd(sa.active_count + (launch & 1), 1);
             }
             if (!fin) {
                 pbar();  // LDS reuse by the next frame of this workgroup
@@ -1478,8 +1495,9 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
             smask = __ballot(act);
         }
     };
+    const int launch = PERSIST ? 0 : streamed_launch(ip, sa);
     if constexpr (!PERSIST) {
-        if (blockIdx.x == 0 && tid == 0) sa.active_count[(ip.launch + 1) & 1] = 0;  // next launch's counter
+        if (blockIdx.x == 0 && tid == 0) sa.active_count[(launch + 1) & 1] = 0;  // next launch's counter
     }
     for (;;) {
         int f;
@@ -1745,7 +1763,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
             for (int i = tid; i < C.n; i += NT) acc[i] = (unsigned long long)as_global(xprev)[i] << 32;
             __syncthreads();
         } else {
-            const int it = ip.launch + 1;
+            const int it = launch + 1;
             phase_a();
             wg_barrier<true>();
             phase_b();
@@ -1760,7 +1778,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
             if (tid == 0) {
                 sa.st[f].iter = it;
                 if (fin) sa.st[f].done = 1;
-                else atomicAdd(sa.active_count + (ip.launch & 1), 1);
+                else atomicAdd(sa.active_count + (launch & 1), 1);
             }
             if (!fin) {
                 wg_barrier<true>();  // LDS reuse by the next frame of this workgroup

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <mutex>
 #include <vector>
 
@@ -47,10 +48,18 @@ struct Workspace {
     int *host_active = nullptr; // pinned
     char *host_meta = nullptr;  // pinned staging for per-call metadata
     size_t host_meta_bytes = 0;
+    // streamed form replayed from a graph: the device launch index, the capture
+    // stream, and the instantiated block of launches with the arguments it holds
+    DevBuf launch_dev;
+    hipStream_t capture = nullptr;
+    hipGraphExec_t graph = nullptr;
+    std::vector<char> graph_key;
     ~Workspace() {
         queue.release(); codes.release(); frame_meta.release();
         z.release(); u.release(); st.release(); active.release(); gslots.release(); gstate.release();
-        gmu.release(); gxprev.release();
+        gmu.release(); gxprev.release(); launch_dev.release();
+        if (graph) (void)hipGraphExecDestroy(graph);
+        if (capture) (void)hipStreamDestroy(capture);
         if (host_active) (void)hipHostFree(host_active);
         if (host_meta) (void)hipHostFree(host_meta);
         if (last) (void)hipEventDestroy(last);
@@ -88,6 +97,7 @@ struct lpdec_code {
     // multi-code launches led by this code: hand out frames of larger codes first
     // (1), in submission order (0), or the default (-1: larger first when sizes differ)
     int tune_order = -1;
+    bool graph = false;  // streamed form: replay each block of launches from a captured graph
     Workspace ws;
     ~lpdec_code() {
         if (d_dc) (void)hipFree(d_dc);

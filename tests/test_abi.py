@@ -116,6 +116,8 @@ def test_tuning_argument_checks(lib):
     vp, i32 = ctypes.c_void_p, ctypes.c_int32
     lib.lpdec_code_set_tuning.argtypes = [vp, i32, i32, i32]
     assert lib.lpdec_code_set_tuning(None, 1, 1, -1) == EINVAL
+    lib.lpdec_code_set_graph.argtypes = [vp, i32]
+    assert lib.lpdec_code_set_graph(None, 1) == EINVAL
     lib.lpdec_code_launch_info.argtypes = [vp, vp, vp]
     assert lib.lpdec_code_launch_info(None, None, None) == EINVAL
     lib.lpdec_autotune.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp]

@@ -99,3 +99,24 @@ def test_multi_autotune_keeps_results_and_records_choice():
     assert len(times) == 8 and all(v > 0 for v in times.values())
     for a, b in zip(ref, run(mode=mode)):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("which", ["36", "48"])
+def test_large_code_held_chunk_variants_agree_bitwise(which):
+    """The n = 16384 codes: every held-chunk variant of the accumulator kernel (and
+    k_decode's walk) in the persistent-global and streamed forms, FP32 and FP16
+    storage, gives bitwise the result of the default launch."""
+    H = W.gallager36(16384) if which == "36" else W.gallager48(16384)
+    code = lp.Code(H)
+    llr = torch.from_numpy(np.concatenate([W.awgn_batch(H, 24, s, tag="held") for s in (2.0, 2.5)])).cuda()
+    kw = dict(W.PAPER_PARAMS, max_iter=40)
+    for mode, storage in ((lp.MODE_PERSISTENT_GLOBAL, 0), (lp.MODE_STREAMED, 0), (lp.MODE_STREAMED, 1)):
+        ref = _decode(code, llr, mode, storage=storage, **kw)
+        for var in (0, 1, 2):
+            code.set_tuning(mode, 0, var)
+            assert code.launch_info(mode=mode, storage=storage)["variant"] == var
+            print(f"({which}) mode {mode} storage {storage} variant {var}", flush=True)
+            got = _decode(code, llr, mode, storage=storage, **kw)
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), (which, mode, storage, var)
+        code.set_tuning(mode, 0, -1)
