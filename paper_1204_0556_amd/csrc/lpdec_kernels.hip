@@ -830,26 +830,45 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                             }
                         }
                     }
-                } else {  // mixed degrees: VB variables per pass, loads first
-                    // var_info entries {slot0 | deg << 24, 1/deg} as one 8-byte word
-                    const auto vinfo = as_global(reinterpret_cast<const unsigned long long *>(C.var_info));
-                    for (int i0 = tid; i0 < C.n; i0 += VB * NT) {
-                        unsigned long long vi[VB];
-                        float g[VB];
+                } else {  // mixed degrees: one degree class at a time
+                    // Variables are numbered by decreasing degree, so a class is a range
+                    // of variables with one degree and consecutive slot blocks: the
+                    // degree is a constant for the class's sums (degrees up to 8; larger
+                    // ones sum in a loop) and a variable's block follows from its index.
+                    // Sums run over the block in slot order, as x_update does.
+                    for (int c = 0; c < C.nvc; ++c) {  // wave-uniform
+                        const int b = C.vc_start[c], end = C.vc_start[c + 1], deg = C.vc_deg[c];
+                        const int s0 = C.vc_slot0[c];
+                        const float inv = C.vc_inv[c];
+                        auto sums = [&](auto dc) {
+                            constexpr int DVC = decltype(dc)::value;
+                            constexpr int VC = 2;  // variables per pass
+                            for (int i0 = b + tid; i0 < end; i0 += VC * NT) {
+                                float g[VC];
 #pragma unroll
-                        for (int t = 0; t < VB; ++t) {
-                            const int i = i0 + t * NT;
-                            vi[t] = (i < C.n) ? vinfo[i] : 0ull;
-                            g[t] = (i < C.n) ? gsrc[i] : 0.0f;
-                        }
+                                for (int t = 0; t < VC; ++t) {
+                                    const int i = i0 + t * NT;
+                                    g[t] = (i < end) ? gsrc[i] : 0.0f;
+                                }
 #pragma unroll
-                        for (int t = 0; t < VB; ++t) {
-                            const int i = i0 + t * NT;
-                            const int lo = (int)(unsigned)vi[t], hi = (int)(unsigned)(vi[t] >> 32);
-                            if (i < C.n)
-                                xs[i] = x_update(slots, VarLoc{lo & 0xffffff, lo >> 24, __int_as_float(hi)},
-                                                 g[t] * gscale);
-                        }
+                                for (int t = 0; t < VC; ++t) {
+                                    const int i = i0 + t * NT;
+                                    if (i < end) {
+                                        const int sb = s0 + (i - b) * deg;
+                                        float a = 0.0f;
+                                        if constexpr (DVC > 0) {
+#pragma unroll
+                                            for (int p = 0; p < DVC; ++p) a += slots[sb + p];
+                                        } else {
+                                            for (int p = 0; p < deg; ++p) a += slots[sb + p];
+                                        }
+                                        xs[i] = clamp01((a - g[t] * gscale) * inv);
+                                    }
+                                }
+                            }
+                        };
+                        if (deg >= 1 && deg <= 8) dispatch_degree<1, 8>(deg, sums);
+                        else sums(std::integral_constant<int, 0>{});
                     }
                 }
             }
