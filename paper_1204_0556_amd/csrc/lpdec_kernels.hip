@@ -200,6 +200,16 @@ hipError_t launch_advance(int *p, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// A value every lane of the wave holds (a frame's code index or offsets), moved to
+// scalar registers so that what is addressed through it (the frame's code table,
+// its LLR and x rows) is addressed with scalar arithmetic.
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Streamed form: iterations every unfinished frame has run before this launch --
 // from the launch's arguments, or from device memory when the launches are
 // replayed from a captured graph (whose arguments are fixed).
@@ -554,9 +564,9 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         }
         if (f >= fb.nframes) break;
 
-        const int ci = fb.code_of_frame ? fb.code_of_frame[f] : 0;
+        const int ci = fb.code_of_frame ? uniform_i32(fb.code_of_frame[f]) : 0;
         const DevCode &C = codes[ci];
-        const int64_t loff = fb.llr_off ? fb.llr_off[f] : (int64_t)f * C.n;
+        const int64_t loff = fb.llr_off ? uniform_i64(fb.llr_off[f]) : (int64_t)f * C.n;
         const float *gam = fb.llr + loff;
         const float thr = ip.tol2 * (float)C.E;
         float *gmu_row = sa.gmu ? sa.gmu + (size_t)(PERSIST ? blockIdx.x : f) * sa.gmu_stride : nullptr;
@@ -1040,7 +1050,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         }
 
         // -- epilogue: x, iteration count and certificate flags (x in LDS) ---------
-        const int64_t xoff = fb.x_off ? fb.x_off[f] : (int64_t)f * C.n;
+        const int64_t xoff = fb.x_off ? uniform_i64(fb.x_off[f]) : (int64_t)f * C.n;
         float frac = 0.0f;
         for (int i = tid; i < C.n; i += NT) {
             const float x = xs[XS * i];
@@ -1292,7 +1302,7 @@ k_decode_pair(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, S
     auto finish_x = [&](auto sc, int f) {
         constexpr int s = decltype(sc)::value;
         const float *xs = lds + s * region + lds_E;
-        const int64_t xoff = fb.x_off ? fb.x_off[f] : (int64_t)f * C.n;
+        const int64_t xoff = fb.x_off ? uniform_i64(fb.x_off[f]) : (int64_t)f * C.n;
         float frac = 0.0f;
         for (int i = tid; i < C.n; i += NT) {
             const float x = xs[i];
@@ -1532,7 +1542,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
             f = next_active();
         }
         if (f >= fb.nframes) break;
-        const int64_t loff = fb.llr_off ? fb.llr_off[f] : (int64_t)f * C.n;
+        const int64_t loff = fb.llr_off ? uniform_i64(fb.llr_off[f]) : (int64_t)f * C.n;
         const float *gam = fb.llr + loff;
         float *gmu_row = sa.gmu ? sa.gmu + (size_t)(PERSIST ? blockIdx.x : f) * sa.gmu_stride : nullptr;
         if constexpr (PERSIST) {
@@ -1806,7 +1816,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
         }
 
         // -- epilogue: x, iteration count and certificate flags ----------------------
-        const int64_t xoff = fb.x_off ? fb.x_off[f] : (int64_t)f * C.n;
+        const int64_t xoff = fb.x_off ? uniform_i64(fb.x_off[f]) : (int64_t)f * C.n;
         float frac = 0.0f;
         for (int i = tid; i < C.n; i += NT) {
             const float x = xs[2 * i];
@@ -1878,9 +1888,9 @@ k_stream_init(const DevCode *__restrict__ codes, FrameBatch fb, StateIO sio, Str
     const int f = blockIdx.x;
     if (f >= fb.nframes) return;
     if (f == 0 && threadIdx.x < 2) sa.active_count[threadIdx.x] = 0;
-    const int ci = fb.code_of_frame ? fb.code_of_frame[f] : 0;
+    const int ci = fb.code_of_frame ? uniform_i32(fb.code_of_frame[f]) : 0;
     const DevCode &C = codes[ci];
-    const int64_t loff = fb.llr_off ? fb.llr_off[f] : (int64_t)f * C.n;
+    const int64_t loff = fb.llr_off ? uniform_i64(fb.llr_off[f]) : (int64_t)f * C.n;
     const int any_bad = frame_invalid(fb, f);
     const size_t base = (size_t)f * C.E_int;
     for (int p = threadIdx.x; p < C.E_int; p += blockDim.x) {
@@ -1898,7 +1908,7 @@ k_stream_init(const DevCode *__restrict__ codes, FrameBatch fb, StateIO sio, Str
         for (int i = threadIdx.x; i < C.n; i += blockDim.x) row[i] = fb.llr[loff + C.var_orig[i]] * mu_inv;
     }
     if (any_bad) {
-        const int64_t xoff = fb.x_off ? fb.x_off[f] : (int64_t)f * C.n;
+        const int64_t xoff = fb.x_off ? uniform_i64(fb.x_off[f]) : (int64_t)f * C.n;
         for (int i = threadIdx.x; i < C.n; i += blockDim.x) fb.x_out[xoff + i] = 0.5f;
     }
     if (threadIdx.x == 0) {
