@@ -291,6 +291,37 @@ def workload_precision(args, lp, W, torch):
     }
 
 
+def large_streamed_llr(W, H):
+    """The 32768-frame streamed batch: the headline's 16384 frames and a second seeded
+    block of 4096 frames at each Eb/N0 (a 2.8 GB working set that only HBM holds)."""
+    return np.concatenate([W.awgn_batch(H, FRAMES_PER_SNR, s) for s in W.HEADLINE_SNRS] +
+                          [W.awgn_batch(H, FRAMES_PER_SNR, s, block=1) for s in W.HEADLINE_SNRS])
+
+
+def workload_streamed_large(args, lp, W, torch):
+    """The streamed (HBM-resident) form alone on the 32768-frame batch, warm-up + steps
+    decodes, against the 8 TB/s roof (used to profile that form by itself)."""
+    H = W.gallager36(2640)
+    code = lp.Code(H)
+    llr = torch.from_numpy(large_streamed_llr(W, H)).cuda()
+    P = dict(W.PAPER_PARAMS, mode=lp.MODE_STREAMED)
+    (x, it, fl), ms = _timed(torch, lambda: lp.decode(code, llr, **P), steps=args.steps, warmup=args.warmup)
+    fi = int(it.cpu().numpy().astype(np.int64).sum())
+    B = algorithmic_bytes_per_frame_iter(H)
+    ach = B * fi / (ms / 1e3) / 1e9
+    return {
+        "metric": METRIC, "value": round(int(llr.shape[0]) * H.n / (ms / 1e3) / 1e6, 2), "unit": "Mbit/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "streamed form: (3,6) n=2640, 32768 frames (two seeded blocks of 4096 at each of "
+                               "1.5/2.0/2.5/3.0 dB), state in HBM, one launch per iteration", "frames": int(llr.shape[0])},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "target_frac": 0.60,
+                     "traffic": profiled_traffic("k_decode_streamed_n2640_large", "traffic_bytes_per_decode"),
+                     "algorithmic_bytes": B * fi, "kernel": "k_decode (streamed)"},
+    }
+
+
 def _cpu_model() -> str:
     """The first processor's identification in /proc/cpuinfo (vendor, model name,
     family/model/stepping, clock, cache) and the machine's processor count."""
@@ -519,7 +550,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the plain and streamed comparisons and the per-Eb/N0 blocks decoded alone")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "uneven", "precision", "serving", "bsc", "sweep", "dual"])
+                    choices=["headline", "uneven", "precision", "serving", "bsc", "sweep", "dual", "streamed_large"])
     ap.add_argument("--bsc-frames", type=int, default=128, help="frames per code and crossover (bsc workload)")
     ap.add_argument("--sweep-frames", type=int, default=4096, help="frames per point (sweep and dual workloads)")
     ap.add_argument("--serving-seconds", type=float, default=1.0,
@@ -566,6 +597,9 @@ def main():
         return
     if args.workload == "dual":
         print(json.dumps(workload_dual(args, lp, W, torch)))
+        return
+    if args.workload == "streamed_large":
+        print(json.dumps(workload_streamed_large(args, lp, W, torch)))
         return
 
     modes = {"auto": lp.MODE_AUTO, "resident": lp.MODE_RESIDENT,
@@ -707,8 +741,7 @@ def main():
         # the headline batch's state (16384 x 63 KB) is of the order of the 256 MB
         # last-level cache; twice the frames (a second seeded block) move a 4.5 GB
         # working set that only HBM holds
-        llr2 = torch.from_numpy(np.concatenate(
-            [llr_h] + [W.awgn_batch(H, FRAMES_PER_SNR, s, block=1) for s in W.HEADLINE_SNRS])).to(dev)
+        llr2 = torch.from_numpy(large_streamed_llr(W, H)).to(dev)
         lp.decode(code, llr2, mode=lp.MODE_STREAMED, **P)
         torch.cuda.synchronize()
         e0.record(stream)
