@@ -58,7 +58,11 @@ typedef enum {
                                       is integral, hence the ML codeword (Sec. 1)       */
 #define LPDEC_FLAG_INVALID 0x80u   /* a non-finite LLR: frame not decoded, x = 1/2      */
 
-/* Message storage precision for the state kept in HBM between iterations. */
+/* Message storage precision of the state kept between iterations (HBM in the
+ * streamed form; registers and per-workgroup scratch in the persistent-global
+ * form).  With FP16 every update rounds z and u to FP16 (nearest even) and all
+ * arithmetic is FP32; the streamed and persistent-global forms then give bitwise
+ * the same results. */
 #define LPDEC_STORAGE_FP32 0
 #define LPDEC_STORAGE_FP16 1 /* z and u = lambda/mu stored as FP16, FP32 compute     */
 
@@ -81,7 +85,11 @@ typedef struct {
                          rho = 1 is Algorithm 1 exactly                                   */
     int32_t max_iter; /* >= 1 (t_max; 1000 in Sec. 5.1)                                   */
     float tol;        /* epsilon >= 0 (1e-5 in Sec. 5.1); 0 disables the stopping test   */
-    int32_t storage;  /* LPDEC_STORAGE_*; FP16 applies to the STREAMED form only          */
+    int32_t storage;  /* LPDEC_STORAGE_*; FP16 applies to the STREAMED form and to the
+                         PERSISTENT_GLOBAL form of one code whose checks all have degree
+                         6 or 8 and whose n is too large for LDS slots (the accumulator
+                         exchange); AUTO with FP16 picks the latter where it exists, else
+                         the former; RESIDENT with FP16: LPDEC_EUNSUPPORTED             */
     int32_t mode;     /* LPDEC_MODE_*                                                     */
 } lpdec_params;
 
@@ -156,8 +164,9 @@ lpdec_status lpdec_decode_state(const lpdec_code *code, int32_t batch, const flo
  * the process ends.  The caller still passes llr, x_out, iters_out and flags_out
  * (device, as lpdec_decode).
  *   - Forms: the persistent ones (mode AUTO, RESIDENT or PERSISTENT_GLOBAL, FP32
- *     storage).  The streamed form and FP16 storage keep every frame's state in
- *     HBM, which the array does not hold: LPDEC_EUNSUPPORTED.
+ *     storage).  The streamed form keeps every frame's state in HBM, which the
+ *     array does not hold, and FP16 storage is not offered here: both give
+ *     LPDEC_EUNSUPPORTED.
  *   - Size: when the persistent-global form needs per-workgroup buffers, the
  *     grid is cut to what the array holds (results do not depend on the grid);
  *     a code whose single workgroup needs more than the array is rejected with

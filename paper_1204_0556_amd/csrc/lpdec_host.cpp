@@ -405,11 +405,14 @@ bool resident_config(const Shape &s, LaunchConfig *cfg, int variant = -1) {
 // from phase A to phase C and walks the others one chunk ahead (KR = -1: k_decode,
 // which walks every chunk without prefetch).  KR is bounded by the 128 registers a
 // lane has at 16 waves per workgroup (the persistent-global form keeps its held
-// chunks live across the whole iteration, so it holds fewer).  variant < 0 picks
-// the default, else the variant-th candidate (clamped).  Returns KR.
-int acc_held_chunks(const Shape &s, bool persistent, int variant, int *nvariants = nullptr) {
+// chunks live across the whole iteration, so it holds fewer).  With FP16 storage
+// the persistent-global form packs a held edge's z and u into one register and holds
+// more: all of a wave's chunks (KR = kAccAllHeld, no walk) when the code has at most
+// that many per wave.  variant < 0 picks the default, else the variant-th candidate
+// (clamped).  Returns KR.
+int acc_held_chunks(const Shape &s, bool persistent, int variant, int *nvariants = nullptr, bool half = false) {
     static const int kStreamed6[] = {-1, 0, 2}, kStreamed8[] = {-1, 0, 2}, kPersist6[] = {-1, 0, 1},
-                     kPersist8[] = {-1, 0, 1};
+                     kPersist8[] = {-1, 0, 1}, kPersistHalf6[] = {kAccAllHeld, 4}, kPersistHalf8[] = {kAccAllHeld, 4};
     // defaults [persistent][degree 8] from the precision batches (8192 frames at
     // 2.5 dB): streamed (3,6) n = 16384 49.8 / 51.2 / 53.8 ms for KR = -1 / 0 / 2,
     // (4,8) 164.5 / 160.2 / 187.5 ms; persistent-global (3,6) 38.0 / 37.5 / 35.5 ms
@@ -417,16 +420,19 @@ int acc_held_chunks(const Shape &s, bool persistent, int variant, int *nvariants
     static const int kDefault[2][2] = {{0, 1}, {2, 2}};
     const int *t = nullptr;
     int nt = 0;
+    const bool ph = persistent && half;
     if (s.dreg == 6) {
-        t = persistent ? kPersist6 : kStreamed6;
-        nt = 3;
+        t = ph ? kPersistHalf6 : (persistent ? kPersist6 : kStreamed6);
+        nt = ph ? (s.cpt <= kAccAllHeld ? 2 : 1) : 3;
+        if (ph && s.cpt > kAccAllHeld) t = kPersistHalf6 + 1;
     } else if (s.dreg == 8) {
-        t = persistent ? kPersist8 : kStreamed8;
-        nt = 3;
+        t = ph ? kPersistHalf8 : (persistent ? kPersist8 : kStreamed8);
+        nt = ph ? (s.cpt <= kAccAllHeld ? 2 : 1) : 3;
+        if (ph && s.cpt > kAccAllHeld) t = kPersistHalf8 + 1;
     }
     if (nvariants) *nvariants = t && s.ncodes == 1 ? nt : 0;
     if (!t || s.ncodes != 1) return -1;
-    const int v = variant < 0 ? kDefault[persistent][s.dreg == 8] : std::min(variant, nt - 1);
+    const int v = variant < 0 ? (ph ? 0 : kDefault[persistent][s.dreg == 8]) : std::min(variant, nt - 1);
     return t[v];
 }
 
@@ -440,21 +446,24 @@ int slot_mode_for(const Shape &s, size_t *lds_bytes) {
     return 0;
 }
 
-void persistent_global_config(const Shape &s, LaunchConfig *cfg, int variant = -1) {
+// FP16 storage: only the accumulator kernel (large codes of check degree 6 or 8);
+// returns false when the code has no such form.
+bool persistent_global_config(const Shape &s, LaunchConfig *cfg, int variant = -1, bool half = false) {
     cfg->form = Form::PersistentGlobal;
     cfg->cpt_tmpl = 0;
     cfg->vpt_tmpl = 0;
     cfg->dclass = s.dclass == 0 ? 0 : 1;
     cfg->dv = 0;
     cfg->slot_mode = slot_mode_for(s, &cfg->lds_bytes);
-    cfg->half = false;
+    cfg->half = half;
     cfg->threads = s.waves * kWave;
     cfg->lds_E = s.Emax;
     cfg->slot_stride = s.Emax;
     cfg->state_stride = s.Eint_max;
-    cfg->acc_kr = cfg->slot_mode == 2 ? acc_held_chunks(s, true, variant) : -1;
+    cfg->acc_kr = cfg->slot_mode == 2 ? acc_held_chunks(s, true, variant, nullptr, half) : -1;
     cfg->acc = cfg->acc_kr >= 0;
     cfg->acc_d = cfg->acc ? s.dreg : 0;
+    return !half || cfg->acc;
 }
 
 // Streamed variants (tuning value): 0 re-reads each chunk's z, u from HBM in every
@@ -534,7 +543,7 @@ WgBytes wg_bytes(const Shape &s, const LaunchConfig &cfg) {
     const bool pg = cfg.form == Form::PersistentGlobal;
     if (s.permuted && cfg.vpt_tmpl == 0) b.gmu = sizeof(float) * (size_t)s.nmax;
     if (pg) {
-        b.state = 2 * sizeof(float) * (size_t)cfg.state_stride;
+        b.state = 2 * (cfg.half ? 2 : sizeof(float)) * (size_t)cfg.state_stride;
         if (cfg.slot_mode == 2) b.xprev = sizeof(unsigned) * (size_t)s.nmax;
         if (cfg.slot_mode == 0) b.slots = sizeof(float) * (size_t)cfg.slot_stride;
     }
@@ -553,17 +562,27 @@ lpdec_status resolve_config(const Shape &s, const lpdec_params &p, bool scattere
                             const lpdec_code *code) {
     const bool half = p.storage == LPDEC_STORAGE_FP16;
     int mode = p.mode;
-    if (half && mode != LPDEC_MODE_STREAMED && mode != LPDEC_MODE_AUTO)
-        return fail(LPDEC_EUNSUPPORTED, "FP16 storage applies to the streamed form only");
-    if (mode == LPDEC_MODE_AUTO) mode = half ? LPDEC_MODE_STREAMED : LPDEC_MODE_RESIDENT;
+    if (half && mode == LPDEC_MODE_RESIDENT)
+        return fail(LPDEC_EUNSUPPORTED, "FP16 storage applies to the streamed and persistent-global forms");
+    if (mode == LPDEC_MODE_AUTO && half) {
+        // FP16: the persistent-global form where the code has it (its held chunks keep
+        // the state in registers: faster than HBM round trips), else the streamed form
+        LaunchConfig probe{};
+        mode = persistent_global_config(s, &probe, -1, true) ? LPDEC_MODE_PERSISTENT_GLOBAL : LPDEC_MODE_STREAMED;
+    }
+    if (mode == LPDEC_MODE_AUTO) mode = LPDEC_MODE_RESIDENT;
     if (mode == LPDEC_MODE_RESIDENT &&
         !resident_config(s, cfg, code ? code->tune_variant[static_cast<int>(Form::Resident)] : -1)) {
         if (p.mode == LPDEC_MODE_RESIDENT)
             return fail(LPDEC_EUNSUPPORTED, "the register-resident form does not fit this code");
         mode = LPDEC_MODE_PERSISTENT_GLOBAL;
     }
-    if (mode == LPDEC_MODE_PERSISTENT_GLOBAL)
-        persistent_global_config(s, cfg, code ? code->tune_variant[static_cast<int>(Form::PersistentGlobal)] : -1);
+    if (mode == LPDEC_MODE_PERSISTENT_GLOBAL &&
+        !persistent_global_config(s, cfg, code ? code->tune_variant[static_cast<int>(Form::PersistentGlobal)] : -1,
+                                  half))
+        return fail(LPDEC_EUNSUPPORTED,
+                    "FP16 storage in the persistent-global form needs one code whose checks all have degree 6 "
+                    "or 8 and whose exchange uses the LDS accumulators (n too large for LDS slots)");
     if (mode == LPDEC_MODE_STREAMED) {
         if (scattered)
             return fail(LPDEC_EUNSUPPORTED, "the streamed form decodes one dense batch of one code per call");
@@ -623,7 +642,7 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
     if (st != LPDEC_OK) return st;
     if (arena && (ncodes > 1 || code_of_frame || ((llr_off || x_off || done) && !arena->host)))
         return fail(LPDEC_EINVAL, "lent scratch serves single-code batches (scattered ones with host staging)");
-    if (arena && cfg.form == Form::Streamed)
+    if (arena && (cfg.form == Form::Streamed || half))
         return fail(LPDEC_EUNSUPPORTED,
                     "the allocation-free decode runs the persistent forms only (FP32 storage, mode AUTO, RESIDENT "
                     "or PERSISTENT_GLOBAL): the streamed form keeps every frame's state in HBM");
@@ -792,8 +811,8 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
             sa.gmu_stride = s.nmax;
         }
         if (pg) {
-            sa.z = p_state;
-            sa.u = static_cast<float *>(p_state) + (size_t)cfg.grid * cfg.state_stride;
+            sa.z = p_state;  // z of every workgroup, then u (FP32, or FP16 values)
+            sa.u = static_cast<char *>(p_state) + (cfg.half ? 2 : sizeof(float)) * (size_t)cfg.grid * cfg.state_stride;
             if (cfg.slot_mode == 2) {
                 sa.gxprev = static_cast<unsigned *>(p_xprev);
                 sa.gmu_stride = s.nmax;
@@ -1053,12 +1072,13 @@ lpdec_status lpdec_code_launch_info(const lpdec_code *code, const lpdec_params *
     out->blocks_per_cu = blocks_per_cu(cfg, code);
     int nacc = 0;
     if (cfg.form != Form::Resident && cfg.slot_mode == 2)
-        acc_held_chunks(shape_of(&code, 1), cfg.form == Form::PersistentGlobal, 0, &nacc);
+        acc_held_chunks(shape_of(&code, 1), cfg.form == Form::PersistentGlobal, 0, &nacc, cfg.half);
     if (nacc > 0) {  // index of the held-chunk count among the code's candidates
         const Shape s = shape_of(&code, 1);
         out->variant = 0;
         for (int v = 0; v < nacc; ++v)
-            if (acc_held_chunks(s, cfg.form == Form::PersistentGlobal, v) == cfg.acc_kr) out->variant = v;
+            if (acc_held_chunks(s, cfg.form == Form::PersistentGlobal, v, nullptr, cfg.half) == cfg.acc_kr)
+                out->variant = v;
     } else if (cfg.form == Form::Streamed) out->variant = cfg.cpt_tmpl == 0 ? 0 : (cfg.staged ? 2 : 1);
     else if (cfg.form == Form::Resident && cfg.dclass == 0 && cfg.dv == 3 && cfg.cpt_tmpl == 2)
         out->variant = cfg.pair ? 1 : 0;
@@ -1098,7 +1118,7 @@ lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, c
     }
     int nacc = 0;  // held-chunk candidates of the large-code kernel
     if (cfg.form != Form::Resident && cfg.slot_mode == 2)
-        acc_held_chunks(shape_of(&one, 1), cfg.form == Form::PersistentGlobal, 0, &nacc);
+        acc_held_chunks(shape_of(&one, 1), cfg.form == Form::PersistentGlobal, 0, &nacc, cfg.half);
     const int nvar = nacc > 0 ? nacc : (cfg.form == Form::Streamed ? 3 : (res_pair ? 2 : 1));
     hipStream_t stream = static_cast<hipStream_t>(stream_v);
     const size_t n = (size_t)code->dc.n;

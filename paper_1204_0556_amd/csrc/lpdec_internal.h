@@ -14,6 +14,7 @@ constexpr int kMaxWaves = kMaxThreads / kWave;
 constexpr int kStageEdges = 8192;
 constexpr int kStageVars = 4096;
 constexpr int kMaxD = 8;           // LPDEC_MAX_CHECK_DEGREE
+constexpr int kAccAllHeld = 8;     // k_decode_acc: held chunks per wave that compile the chunk walk out
 
 // A pointer read from memory (a code table, an argument structure) is generic to
 // the compiler, and a generic load also waits on LDS traffic; these mark one as

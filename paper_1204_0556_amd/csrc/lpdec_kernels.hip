@@ -287,6 +287,11 @@ __device__ __forceinline__ const T *opaque_ptr(const T *p) {
     return p;
 }
 
+// Row `off` (wave-uniform) of a lane-minor table, its address in scalar registers.
+__device__ __forceinline__ const __attribute__((address_space(1))) int *csr_row(const int *table, int off) {
+    return as_global(opaque_ptr(table)) + __builtin_amdgcn_readfirstlane(off);
+}
+
 // Degree, offset and check count of chunk c (c wave-uniform).
 struct ChunkDesc {
     int deg, off, cnt;
@@ -408,6 +413,12 @@ __device__ __forceinline__ void st_state(void *p, size_t i, float a) {
     if constexpr (HALF) as_global_rw(static_cast<unsigned short *>(p))[i] = __half_as_ushort(__float2half_rn(a));
     else as_global_rw(static_cast<float *>(p))[i] = a;
 }
+// Two FP16 state values in one register (a in the low half), rounded as st_state rounds.
+__device__ __forceinline__ unsigned pack_h2(float a, float b) {
+    return (unsigned)__half_as_ushort(__float2half_rn(a)) | ((unsigned)__half_as_ushort(__float2half_rn(b)) << 16);
+}
+__device__ __forceinline__ float lo_h2f(unsigned v) { return __half2float(__ushort_as_half((unsigned short)(v & 0xffffu))); }
+__device__ __forceinline__ float hi_h2f(unsigned v) { return __half2float(__ushort_as_half((unsigned short)(v >> 16))); }
 
 // ---------------------------------------------------------------------------
 // The decoder kernel.
@@ -1472,13 +1483,21 @@ k_decode_pair(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, S
 // sums and the exchange are those of k_decode, so results are bitwise the same.
 // Chunks are padded to 64 lanes in every array, so a held chunk's rows are loaded
 // for all lanes without a branch (padding lanes take no part in the update).
+// FP16 storage in the persistent-global form keeps a held edge's z and u as two
+// FP16 values in one register (z in the low half) and the walked chunks' state as
+// FP16 in the workgroup's scratch; each update rounds z and u to FP16 as the
+// streamed form's stores do, so the two forms' results are bitwise the same.  Half
+// the registers per held chunk lets the (3,6) n = 16384 code hold all its chunks.
 template <int D, int KR, bool HALF, bool PERSIST>
 __global__ void __launch_bounds__(kMaxThreads, 1)
 k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateIO sio, StreamArgs sa,
              int state_stride) {
-    static_assert(!PERSIST || !HALF, "FP16 storage is a streamed-form option");
     static_assert(KR >= 0, "held chunks per wave");
     constexpr int KH = KR > 0 ? KR : 1;  // register arrays of the held chunks
+    constexpr bool PK = HALF && PERSIST;  // held chunks as packed FP16 pairs
+    // KR = kAccAllHeld: every chunk of a wave is held (the host launches it only for
+    // codes of at most that many chunks per wave), and the chunk walk is compiled out
+    constexpr bool WALK = KR < kAccAllHeld;
     extern __shared__ __attribute__((aligned(16))) float lds[];
     __shared__ float s_red[2][2][kMaxWaves];
     __shared__ int s_frame;
@@ -1506,7 +1525,8 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
         hoff[k] = h.off;
         hval[k] = has && lane < h.cnt;
     }
-    float zr[KH][D], ur[KH][D];
+    float zr[PK ? 1 : KH][D], ur[PK ? 1 : KH][D];
+    unsigned hr[PK ? KH : 1][D];  // PK: z | u << 16 (FP16 bits) of held edge e of chunk k
 
     int sbase = (int)blockIdx.x - kWave * (int)gridDim.x;
     unsigned long long smask = 0ull;
@@ -1580,12 +1600,18 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                 for (int e = 0; e < D; ++e) {
                     float z0 = 0.0f, u0 = 0.0f;
                     if (sio.z_in && hval[k]) {
-                        const int ce = C.edge_csr[hoff[k] + e * kWave + lane];
+                        // row address scalar, table pointer opaque: nothing per edge is
+                        // hoisted out of the frame loop into registers
+                        const int ce = csr_row(C.edge_csr, hoff[k] + e * kWave)[lane];
                         z0 = sio.z_in[fb0 + ce];
                         u0 = sio.u_in[fb0 + ce];
                     }
-                    zr[k][e] = z0;
-                    ur[k][e] = u0;
+                    if constexpr (PK) {
+                        hr[k][e] = pack_h2(z0, u0);
+                    } else {
+                        zr[k][e] = z0;
+                        ur[k][e] = u0;
+                    }
                 }
             for (int k = KR; k < cpt; ++k) {
                 const int c = wave + k * W;
@@ -1599,8 +1625,8 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                         z0 = sio.z_in[fb0 + ce];
                         u0 = sio.u_in[fb0 + ce];
                     }
-                    st_state<false>(gz, p, z0);
-                    st_state<false>(gu, p, u0);
+                    st_state<HALF>(gz, p, z0);
+                    st_state<HALF>(gu, p, u0);
                 }
             }
         }
@@ -1659,13 +1685,18 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                     }
                     if (hval[k]) {
 #pragma unroll
-                        for (int e = 0; e < D; ++e)
-                            atomicAdd(acc + (mcur[e] & 0xffffu), to_fixed(zr[k][e] - ur[k][e]));
+                        for (int e = 0; e < D; ++e) {
+                            const float w = PK ? lo_h2f(hr[k][e]) - hi_h2f(hr[k][e]) : zr[PK ? 0 : k][e] - ur[PK ? 0 : k][e];
+                            atomicAdd(acc + (mcur[e] & 0xffffu), to_fixed(w));
+                        }
                     }
 #pragma unroll
                     for (int e = 0; e < D; ++e) mcur[e] = mnext[e];
+                    // many held chunks: one chunk's conversions at a time
+                    if constexpr (PK) __builtin_amdgcn_sched_barrier(0);
                 }
             }
+            if constexpr (!WALK) return;
             Walk cur = walk_at(KR);
             float zc[D], uc[D];
             uint32_t mc[D];
@@ -1710,7 +1741,20 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
 #pragma unroll
                 for (int k = 0; k < KR; ++k) {
                     if (k + 1 < KR) load_meta<D>(mnext, C.edge_meta, hoff[k + 1], D, lane);
-                    if (hval[k]) {
+                    if constexpr (PK) {
+                        if (hval[k]) {
+                            float zz[D], uu[D];
+#pragma unroll
+                            for (int e = 0; e < D; ++e) {
+                                zz[e] = lo_h2f(hr[k][e]);
+                                uu[e] = hi_h2f(hr[k][e]);
+                            }
+                            check_update<D, 2>(zz, uu, mcur, xs, ip.rho, rp, rd);
+#pragma unroll
+                            for (int e = 0; e < D; ++e) hr[k][e] = pack_h2(zz[e], uu[e]);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    } else if (hval[k]) {
                         check_update<D, 2>(zr[k], ur[k], mcur, xs, ip.rho, rp, rd);
                         if constexpr (!PERSIST) {
 #pragma unroll
@@ -1725,6 +1769,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                     for (int e = 0; e < D; ++e) mcur[e] = mnext[e];
                 }
             }
+            if constexpr (!WALK) return;
             Walk cur = walk_at(KR);
             float zc[D], uc[D];
             uint32_t mc[D];
@@ -1858,9 +1903,9 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
 #pragma unroll
                     for (int e = 0; e < D; ++e)
                         if (hval[k]) {
-                            const int ce = C.edge_csr[hoff[k] + e * kWave + lane];
-                            sio.z_out[fb0 + ce] = zr[k][e];
-                            sio.u_out[fb0 + ce] = ur[k][e];
+                            const int ce = csr_row(C.edge_csr, hoff[k] + e * kWave)[lane];
+                            sio.z_out[fb0 + ce] = PK ? lo_h2f(hr[k][e]) : zr[PK ? 0 : k][e];
+                            sio.u_out[fb0 + ce] = PK ? hi_h2f(hr[k][e]) : ur[PK ? 0 : k][e];
                         }
                 for (int k = KR; k < cpt; ++k) {
                     const int c = wave + k * W;
@@ -1870,8 +1915,8 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                         for (int e = 0; e < D; ++e) {
                             const size_t p = h.off + e * kWave + lane;
                             const int ce = C.edge_csr[p];
-                            sio.z_out[fb0 + ce] = ld_state<false>(gz, p);
-                            sio.u_out[fb0 + ce] = ld_state<false>(gu, p);
+                            sio.z_out[fb0 + ce] = ld_state<HALF>(gz, p);
+                            sio.u_out[fb0 + ce] = ld_state<HALF>(gu, p);
                         }
                     }
                 }
@@ -2083,7 +2128,9 @@ static hipError_t go_acc(const LaunchConfig &cfg, const DevCode *codes, const Fr
         return go_acc1<D, KR, false, false>(cfg, codes, fb, ip, sio, sa, stream, q);              \
     }
 #define LPD_ACC_P(D, KR) \
-    if (pg && cfg.acc_d == D && cfg.acc_kr == KR) return go_acc1<D, KR, false, true>(cfg, codes, fb, ip, sio, sa, stream, q);
+    if (pg && !cfg.half && cfg.acc_d == D && cfg.acc_kr == KR) return go_acc1<D, KR, false, true>(cfg, codes, fb, ip, sio, sa, stream, q);
+#define LPD_ACC_PH(D, KR) \
+    if (pg && cfg.half && cfg.acc_d == D && cfg.acc_kr == KR) return go_acc1<D, KR, true, true>(cfg, codes, fb, ip, sio, sa, stream, q);
     if (cfg.form == Form::Resident) return hipErrorInvalidValue;
     LPD_ACC_S(6, 0)
     LPD_ACC_S(6, 2)
@@ -2093,8 +2140,13 @@ static hipError_t go_acc(const LaunchConfig &cfg, const DevCode *codes, const Fr
     LPD_ACC_P(6, 1)
     LPD_ACC_P(8, 0)
     LPD_ACC_P(8, 1)
+    LPD_ACC_PH(6, 8)
+    LPD_ACC_PH(6, 4)
+    LPD_ACC_PH(8, 4)
+    LPD_ACC_PH(8, 8)
 #undef LPD_ACC_S
 #undef LPD_ACC_P
+#undef LPD_ACC_PH
     return hipErrorInvalidValue;
 }
 

@@ -120,3 +120,44 @@ def test_large_code_held_chunk_variants_agree_bitwise(which):
             for a, b in zip(ref, got):
                 assert np.array_equal(a, b), (which, mode, storage, var)
         code.set_tuning(mode, 0, -1)
+
+
+@pytest.mark.parametrize("which", ["36", "48"])
+def test_fp16_persistent_global_equals_streamed(which):
+    """FP16 storage in the persistent-global form (held chunks as packed FP16 pairs in
+    registers, the rest in FP16 scratch) rounds exactly as the streamed form's FP16
+    stores do: bitwise the same x, iterations and flags, for every held-chunk variant,
+    from a zero start and from an exported state."""
+    H = W.gallager36(16384) if which == "36" else W.gallager48(16384)
+    code = lp.Code(H)
+    llr = torch.from_numpy(np.concatenate([W.awgn_batch(H, 24, s, tag="half-pg") for s in (2.0, 2.5)])).cuda()
+    kw = dict(W.PAPER_PARAMS, max_iter=60, storage=lp.STORAGE_FP16)
+    ref = _decode(code, llr, lp.MODE_STREAMED, **kw)
+    for var in (0, 1):
+        code.set_tuning(lp.MODE_PERSISTENT_GLOBAL, 0, var)
+        li = code.launch_info(mode=lp.MODE_PERSISTENT_GLOBAL, storage=lp.STORAGE_FP16)
+        print(f"({which}) FP16 persistent-global variant {var}: {li}", flush=True)
+        got = _decode(code, llr, lp.MODE_PERSISTENT_GLOBAL, **kw)
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b), (which, var)
+    code.set_tuning(lp.MODE_PERSISTENT_GLOBAL, 0, -1)
+    # 12 + 18 iterations through the exported (FP16-valued) state equal 30 in one go
+    sub = llr[:6].contiguous()
+    kw = dict(tol=0.0, storage=lp.STORAGE_FP16, mode=lp.MODE_PERSISTENT_GLOBAL)
+    a = lp.decode_state(code, sub, max_iter=30, **kw)
+    b = lp.decode_state(code, sub, max_iter=12, **kw)
+    c = lp.decode_state(code, sub, z=b[3], u=b[4], state_in=True, max_iter=18, **kw)
+    s = lp.decode_state(code, sub, max_iter=30, tol=0.0, storage=lp.STORAGE_FP16, mode=lp.MODE_STREAMED)
+    for k in (0, 3, 4):
+        assert np.array_equal(a[k].cpu().numpy(), c[k].cpu().numpy())
+        assert np.array_equal(a[k].cpu().numpy(), s[k].cpu().numpy())
+
+
+def test_fp16_persistent_global_needs_an_accumulator_code():
+    # n = 2640 exchanges through LDS float slots: no FP16 persistent-global kernel
+    code = lp.Code(W.gallager36(2640))
+    llr = torch.from_numpy(W.awgn_batch(W.gallager36(2640), 4, 2.5, tag="half-pg-no")).cuda()
+    with pytest.raises(lp.LpdecError):
+        lp.decode(code, llr, mode=lp.MODE_PERSISTENT_GLOBAL, storage=lp.STORAGE_FP16)
+    with pytest.raises(lp.LpdecError):
+        lp.decode(code, llr, mode=lp.MODE_RESIDENT, storage=lp.STORAGE_FP16)
