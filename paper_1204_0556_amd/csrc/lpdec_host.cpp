@@ -336,7 +336,8 @@ int single_busiest(int nchunks, int W) {
 // Resident form: z,u in registers, slots and x in LDS.  Degree-6 codes: cpt <= 2
 // chunks per wave with their metadata, gamma/mu of <= 8 variables per thread,
 // <= 768 threads; one code whose variables all have degree 3 may run two frames
-// per workgroup (variant 1; the default when it evens out the SIMDs' chunks).
+// per workgroup (variant 1; the default when it evens out the SIMDs' chunks);
+// cpt 3..4 at up to 16 waves with the metadata and gamma/mu read from memory.
 // Check degrees 6..8: cpt <= 8 chunks per wave, metadata and variable tables
 // read from memory.
 bool resident_config(const Shape &s, LaunchConfig *cfg, int variant = -1) {
@@ -362,8 +363,28 @@ bool resident_config(const Shape &s, LaunchConfig *cfg, int variant = -1) {
         return true;
     }
     if (s.dclass != 0) return false;  // register budget only holds for degree-6 codes
-    if (s.cpt > 2) return false;
+    if (s.cpt > 4) return false;
     const int threads = s.waves * kWave;
+    if (s.cpt > 2) {
+        // three or four chunks per wave (codes up to 64 chunks, n up to about 8192 at
+        // rate 1/2): up to 16 waves, z and u in registers, the edge metadata and
+        // gamma/mu read from memory each iteration (the registers hold the state only)
+        const size_t lds = 4 * ((size_t)s.Emax + s.nmax);
+        if (threads > kMaxThreads || lds + kStaticLds > kLdsLimit) return false;
+        cfg->form = Form::Resident;
+        cfg->cpt_tmpl = 4;
+        cfg->vpt_tmpl = 0;
+        cfg->dclass = 0;
+        cfg->dv = (s.dv == 3) ? 3 : 0;
+        cfg->slot_mode = 1;
+        cfg->half = false;
+        cfg->threads = threads;
+        cfg->lds_bytes = lds;
+        cfg->lds_E = s.Emax;
+        cfg->slot_stride = 0;
+        cfg->state_stride = 0;
+        return true;
+    }
     if (threads > 768) return false;
     const int vpt = (s.nmax + threads - 1) / threads;
     if (vpt > 8) return false;

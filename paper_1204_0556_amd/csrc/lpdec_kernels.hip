@@ -478,10 +478,11 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
     constexpr int NC = CPT > 0 ? CPT : 1;
     float z[NC][DMAX], u[NC][DMAX];
     // Packed edge metadata of the register-held chunks: kept in registers for
-    // degree-6 codes; with checks of degree up to 8 the registers hold only z and
-    // u (up to eight chunks per wave), and the metadata (per code, shared by every
-    // frame, so L2-resident) is loaded again each iteration, one chunk ahead.
-    constexpr bool MREG = DMAX <= 6;
+    // degree-6 codes with up to two chunks per wave; with checks of degree up to 8,
+    // or four chunks per wave, the registers hold only z and u, and the metadata
+    // (per code, shared by every frame, so L2-resident) is loaded again each
+    // iteration, one chunk ahead.
+    constexpr bool MREG = DMAX <= 6 && CPT <= 2;
     // register-resident form: phase C writes each chunk's slots for the next
     // iteration right after updating it (phase A fused into phase C; phase C
     // reads only x, never the slots).  With metadata from memory this halves its
@@ -673,7 +674,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                     for (int e = 0; e < DMAX; ++e) {
                         float z0 = 0.0f, u0 = 0.0f;
                         if (sio.z_in && cval[k] && e < cdeg[k]) {
-                            const int ce = C.edge_csr[coff[k] + e * kWave + lane];
+                            const int ce = csr_row(C.edge_csr, coff[k] + e * kWave)[lane];
                             z0 = sio.z_in[sbase + ce];
                             u0 = sio.u_in[sbase + ce];
                         }
@@ -1106,7 +1107,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
 #pragma unroll
                     for (int e = 0; e < DMAX; ++e)
                         if (cval[k] && e < cdeg[k]) {
-                            const int ce = C.edge_csr[coff[k] + e * kWave + lane];
+                            const int ce = csr_row(C.edge_csr, coff[k] + e * kWave)[lane];
                             sio.z_out[sbase + ce] = z[k][e];
                             sio.u_out[sbase + ce] = u[k][e];
                         }
@@ -2023,6 +2024,8 @@ static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const 
                 if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8 && cfg.dv == 3) LPD_GO(2, 8, true, true, 1, false, 768, 3);
                 if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 4) LPD_GO(2, 4, true, true, 1, false, 768);
                 if (cfg.cpt_tmpl == 2 && cfg.vpt_tmpl == 8) LPD_GO(2, 8, true, true, 1, false, 768);
+                if (cfg.cpt_tmpl == 4 && cfg.dv == 3) LPD_GO(4, 0, true, true, 1, false, 1024, 3);
+                if (cfg.cpt_tmpl == 4) LPD_GO(4, 0, true, true, 1, false, 1024);
             }
             // checks of degree 6..8: z, u of up to eight chunks per wave in registers,
             // variables read from the code's tables (VPT 0); the more chunks per

@@ -89,10 +89,15 @@ def test_messages_after_k_iterations(K, mode):
         assert np.abs(u - ref.u).max() < 1e-4
 
 
-def test_forms_agree_bitwise():
-    H = W.gallager36(2640)
+@pytest.mark.parametrize("n", [2640, 4608, 8064])
+def test_forms_agree_bitwise(n):
+    # n = 4608 and 8064 run the resident form with three and four chunks per wave
+    # (16 waves, metadata and gamma/mu read from memory each iteration)
+    H = W.gallager36(n)
     llr = W.awgn_batch(H, 32, 2.0, tag="forms")
     code = lp.Code(H)
+    assert code.info["resident_capable"]
+    print(f"forms n={n}: {code.launch_info(mode=lp.MODE_RESIDENT)}", flush=True)
     outs = []
     for m in (lp.MODE_RESIDENT, lp.MODE_PERSISTENT_GLOBAL, lp.MODE_STREAMED):
         x, it, fl = lp.decode(code, dev(llr), mode=m, max_iter=300)
@@ -205,8 +210,9 @@ def test_invalid_frames_are_flagged():
             assert fl[f] & lp.FLAG_CONVERGED
 
 
-def test_warm_start_resume_is_exact():
-    H = W.gallager36(2640)
+@pytest.mark.parametrize("n", [2640, 8064])
+def test_warm_start_resume_is_exact(n):
+    H = W.gallager36(n)
     llr = W.awgn_batch(H, 4, 1.5, tag="warm")
     code = lp.Code(H)
     for m in (lp.MODE_RESIDENT, lp.MODE_STREAMED):
