@@ -274,7 +274,17 @@ typedef struct {
                                       SIMDs of a CU hold even shares of the chunks (the
                                       default where that shortens the check phase, for
                                       batches of at least two frames per CU; smaller
-                                      batches run variant 0).  -1 otherwise             */
+                                      batches run variant 0).
+                                      Large codes whose checks all have degree 6 or 8
+                                      (the LDS accumulator exchange), chunks a wave holds
+                                      in registers: streamed form 0 none (every phase
+                                      walks the chunks), 1 none (walk one chunk ahead,
+                                      the default for degree 8), 2 two; persistent-global
+                                      FP32 0 none, 1 none (one ahead), 2 one (default), 3
+                                      all, with two of the plan's waves per hardware wave
+                                      (degree 6, at most 8 chunks per wave);
+                                      persistent-global FP16 0 all (default; at most 8
+                                      chunks per wave), 1 four.  -1 otherwise            */
 } lpdec_launch_info;
 
 /* The launch a decode of `code` with parameters `p` (NULL = defaults; mode and
@@ -282,17 +292,22 @@ typedef struct {
 lpdec_status lpdec_code_launch_info(const lpdec_code *code, const lpdec_params *p,
                                     lpdec_launch_info *out);
 
+/* Variants a form can have (lpdec_launch_info.variant lies in 0..LPDEC_TUNE_VARIANTS-1). */
+#define LPDEC_TUNE_VARIANTS 4
+
 /* Fix the launch of one form (LPDEC_MODE_RESIDENT, _STREAMED or
  * _PERSISTENT_GLOBAL) for this code.
  *   blocks_per_cu  workgroups per CU, 1..32; 0 restores the runtime's estimate
- *   variant        see lpdec_launch_info.variant.  Streamed form: 0, 1 or 2; a
- *                  variant the code does not allow falls back to the next lower
- *                  one; -1 restores the default (the highest allowed).  Resident
- *                  form: 0 one frame per workgroup; 1 two frames per workgroup for
- *                  every batch size (0 where the code does not allow it); -1
- *                  restores the default (two frames where they help, for batches
- *                  of at least two frames per CU).  Ignored by the
- *                  persistent-global form.
+ *   variant        see lpdec_launch_info.variant, -1..LPDEC_TUNE_VARIANTS-1.
+ *                  Streamed form: 0, 1 or 2; a variant the code does not allow
+ *                  falls back to the next lower one; -1 restores the default (the
+ *                  highest allowed).  Resident form: 0 one frame per workgroup; 1
+ *                  two frames per workgroup for every batch size (0 where the code
+ *                  does not allow it); -1 restores the default (two frames where
+ *                  they help, for batches of at least two frames per CU).  Large
+ *                  codes with the accumulator exchange: the held-chunk candidate
+ *                  (clamped to the last one the code allows).  Ignored by the
+ *                  persistent-global form of other codes.
  * Not synchronised with decodes running on other threads. */
 lpdec_status lpdec_code_set_tuning(lpdec_code *code, int32_t mode, int32_t blocks_per_cu,
                                    int32_t variant);
@@ -317,7 +332,7 @@ lpdec_status lpdec_code_set_graph(lpdec_code *code, int32_t enable);
  * fastest for the form `p` resolves to.  Synchronous.
  *   best_out  host [2], may be NULL: the chosen blocks_per_cu and variant (-1
  *             for forms without variants)
- *   ms_out    host [3*max_blocks_per_cu], may be NULL: time of candidate
+ *   ms_out    host [LPDEC_TUNE_VARIANTS*max_blocks_per_cu], may be NULL: time of candidate
  *             (variant v, blocks b) at [v*max_blocks_per_cu + b - 1] (forms with
  *             variants), or at [b - 1] (others); -1 where not run
  * Scratch outputs are allocated and freed inside the call. */

@@ -36,6 +36,7 @@ EXECUTOR_GPU, EXECUTOR_HOST_NULL = 0, 1
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 EVAL_WORD_ERROR, EVAL_CODEWORD, EVAL_ML_ERROR = 0x01, 0x02, 0x04
 MAX_CHECK_DEGREE = 8
+TUNE_VARIANTS = 4  # LPDEC_TUNE_VARIANTS
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED", -5: "EBUSY"}
 
@@ -250,12 +251,12 @@ class Code:
         p = _params(**params)
         mb = int(max_blocks_per_cu)
         best = (ctypes.c_int32 * 2)()
-        ms = (ctypes.c_float * (3 * mb))()
+        ms = (ctypes.c_float * (TUNE_VARIANTS * mb))()
         _check(_lib.lpdec_autotune(self.handle, B, _dev_ptr(llr, torch.float32, "llr"), ctypes.byref(p),
                                    mb, best, ms, _stream(stream)))
         # entries of variant v at [v * mb + b]; forms without variants use v = 0 and report -1
         times = {}
-        for v in range(3):
+        for v in range(TUNE_VARIANTS):
             for b in range(mb):
                 if ms[v * mb + b] >= 0:
                     times[(v if best[1] >= 0 else -1, b + 1)] = float(ms[v * mb + b])

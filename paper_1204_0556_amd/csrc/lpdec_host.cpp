@@ -429,10 +429,12 @@ bool resident_config(const Shape &s, LaunchConfig *cfg, int variant = -1) {
 // chunks live across the whole iteration, so it holds fewer).  With FP16 storage
 // the persistent-global form packs a held edge's z and u into one register and holds
 // more: all of a wave's chunks (KR = kAccAllHeld, no walk) when the code has at most
-// that many per wave.  variant < 0 picks the default, else the variant-th candidate
-// (clamped).  Returns KR.
+// that many per wave.  FP32 persistent-global degree-6 codes of at most that many
+// chunks per wave may also hold everything with two plan waves per hardware wave
+// (returned as 2 kAccAllHeld: half the waves, twice the registers each).  variant < 0
+// picks the default, else the variant-th candidate (clamped).  Returns KR.
 int acc_held_chunks(const Shape &s, bool persistent, int variant, int *nvariants = nullptr, bool half = false) {
-    static const int kStreamed6[] = {-1, 0, 2}, kStreamed8[] = {-1, 0, 2}, kPersist6[] = {-1, 0, 1},
+    static const int kStreamed6[] = {-1, 0, 2}, kStreamed8[] = {-1, 0, 2}, kPersist6[] = {-1, 0, 1, 2 * kAccAllHeld},
                      kPersist8[] = {-1, 0, 1}, kPersistHalf6[] = {kAccAllHeld, 4}, kPersistHalf8[] = {kAccAllHeld, 4};
     // defaults [persistent][degree 8] from the precision batches (8192 frames at
     // 2.5 dB): streamed (3,6) n = 16384 49.8 / 51.2 / 53.8 ms for KR = -1 / 0 / 2,
@@ -446,6 +448,7 @@ int acc_held_chunks(const Shape &s, bool persistent, int variant, int *nvariants
         t = ph ? kPersistHalf6 : (persistent ? kPersist6 : kStreamed6);
         nt = ph ? (s.cpt <= kAccAllHeld ? 2 : 1) : 3;
         if (ph && s.cpt > kAccAllHeld) t = kPersistHalf6 + 1;
+        if (persistent && !half && s.cpt <= kAccAllHeld && s.waves >= 2) nt = 4;
     } else if (s.dreg == 8) {
         t = ph ? kPersistHalf8 : (persistent ? kPersist8 : kStreamed8);
         nt = ph ? (s.cpt <= kAccAllHeld ? 2 : 1) : 3;
@@ -453,7 +456,10 @@ int acc_held_chunks(const Shape &s, bool persistent, int variant, int *nvariants
     }
     if (nvariants) *nvariants = t && s.ncodes == 1 ? nt : 0;
     if (!t || s.ncodes != 1) return -1;
-    const int v = variant < 0 ? (ph ? 0 : kDefault[persistent][s.dreg == 8]) : std::min(variant, nt - 1);
+    // FP32 persistent-global degree 6: every chunk held at two plan waves per wave where
+    // the code allows it ((3,6) n = 16384: 29.4 ms against 35.7 ms for one held chunk)
+    const int def = ph ? 0 : (persistent && s.dreg == 6 && nt == 4 ? 3 : kDefault[persistent][s.dreg == 8]);
+    const int v = variant < 0 ? def : std::min(variant, nt - 1);
     return t[v];
 }
 
@@ -484,6 +490,7 @@ bool persistent_global_config(const Shape &s, LaunchConfig *cfg, int variant = -
     cfg->acc_kr = cfg->slot_mode == 2 ? acc_held_chunks(s, true, variant, nullptr, half) : -1;
     cfg->acc = cfg->acc_kr >= 0;
     cfg->acc_d = cfg->acc ? s.dreg : 0;
+    if (cfg->acc_kr == 2 * kAccAllHeld) cfg->threads = (s.waves + 1) / 2 * kWave;  // two plan waves per wave
     return !half || cfg->acc;
 }
 
@@ -504,7 +511,7 @@ void streamed_config(const Shape &s, bool half, LaunchConfig *cfg, int variant =
                           s.Eint_max <= kStageEdges && s.Emax <= kStageEdges && s.nmax <= kStageVars &&
                           s.nmax <= 4 * threads && stage_lds + kStaticLds <= kLdsLimit;
     if (variant == 0) cfg->cpt_tmpl = 0;
-    cfg->staged = stage_ok && variant == 2;
+    cfg->staged = stage_ok && variant >= 2;
     if (cfg->staged) cfg->lds_bytes = 0;
     cfg->vpt_tmpl = 0;
     cfg->dv = 0;
@@ -1112,7 +1119,8 @@ lpdec_status lpdec_code_set_tuning(lpdec_code *code, int32_t mode, int32_t bpc, 
     const int f = form_of_mode(mode);
     if (f < 0) return fail(LPDEC_EINVAL, "mode must be RESIDENT, STREAMED or PERSISTENT_GLOBAL (got %d)", mode);
     if (bpc < 0 || bpc > 32) return fail(LPDEC_EINVAL, "blocks_per_cu must lie in 0..32 (got %d)", bpc);
-    if (variant < -1 || variant > 2) return fail(LPDEC_EINVAL, "variant must lie in -1..2 (got %d)", variant);
+    if (variant < -1 || variant >= LPDEC_TUNE_VARIANTS)
+        return fail(LPDEC_EINVAL, "variant must lie in -1..%d (got %d)", LPDEC_TUNE_VARIANTS - 1, variant);
     code->tune_bpc[f] = bpc;
     code->tune_variant[f] = variant;
     return LPDEC_OK;
@@ -1140,7 +1148,7 @@ lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, c
     int nacc = 0;  // held-chunk candidates of the large-code kernel
     if (cfg.form != Form::Resident && cfg.slot_mode == 2)
         acc_held_chunks(shape_of(&one, 1), cfg.form == Form::PersistentGlobal, 0, &nacc, cfg.half);
-    const int nvar = nacc > 0 ? nacc : (cfg.form == Form::Streamed ? 3 : (res_pair ? 2 : 1));
+    const int nvar = std::min(LPDEC_TUNE_VARIANTS, nacc > 0 ? nacc : (cfg.form == Form::Streamed ? 3 : (res_pair ? 2 : 1)));
     hipStream_t stream = static_cast<hipStream_t>(stream_v);
     const size_t n = (size_t)code->dc.n;
     float *x = nullptr;
@@ -1151,7 +1159,7 @@ lpdec_status lpdec_autotune(lpdec_code *code, int32_t batch, const float *llr, c
     int best = 0, best_var = -1;
     float best_ms = 0.0f;
     if (ms_out)
-        for (int k = 0; k < 3 * max_bpc; ++k) ms_out[k] = -1.0f;
+        for (int k = 0; k < LPDEC_TUNE_VARIANTS * max_bpc; ++k) ms_out[k] = -1.0f;
     auto run = [&]() -> lpdec_status {
         HIP_TRY(hipMalloc(&x, sizeof(float) * n * batch));
         HIP_TRY(hipMalloc(&it, sizeof(int32_t) * batch));

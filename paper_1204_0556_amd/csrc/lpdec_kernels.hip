@@ -1489,8 +1489,13 @@ k_decode_pair(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, S
 // FP16 in the workgroup's scratch; each update rounds z and u to FP16 as the
 // streamed form's stores do, so the two forms' results are bitwise the same.  Half
 // the registers per held chunk lets the (3,6) n = 16384 code hold all its chunks.
-template <int D, int KR, bool HALF, bool PERSIST>
-__global__ void __launch_bounds__(kMaxThreads, 1)
+// VW = 2 (persistent-global, every chunk held): each hardware wave hosts two of the
+// plan's waves (wave w and w + NW), so a workgroup of half the waves has twice the
+// registers per wave and holds an FP32 frame of the (3,6) n = 16384 code whole.  The
+// residuals are kept and published per plan wave, so the stopping test sums the same
+// partial sums in the same order as with one plan wave per hardware wave.
+template <int D, int KR, bool HALF, bool PERSIST, int VW = 1>
+__global__ void __launch_bounds__(kMaxThreads / VW, 1)
 k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateIO sio, StreamArgs sa,
              int state_stride) {
     static_assert(KR >= 0, "held chunks per wave");
@@ -1499,6 +1504,9 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
     // KR = kAccAllHeld: every chunk of a wave is held (the host launches it only for
     // codes of at most that many chunks per wave), and the chunk walk is compiled out
     constexpr bool WALK = KR < kAccAllHeld;
+    static_assert(VW == 1 || (VW == 2 && PERSIST && !WALK), "two plan waves per wave: all chunks held");
+    constexpr int NH = VW * KR;                // held chunks per hardware wave
+    constexpr int NHA = NH > 0 ? NH : 1;
     extern __shared__ __attribute__((aligned(16))) float lds[];
     __shared__ float s_red[2][2][kMaxWaves];
     __shared__ int s_frame;
@@ -1508,26 +1516,27 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
     const int NT = blockDim.x;
     const int NW = NT >> 6;
     const DevCode &C = codes[0];
-    const int W = C.waves, cpt = C.cpt;
+    const int W = C.waves, cpt = C.cpt;  // the plan's waves (NW = W when VW = 1)
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(lds);
     const float *xs = lds + 1;  // x sits in each accumulator's high word (stride 2)
     unsigned *xprev = PERSIST ? sa.gxprev + (size_t)blockIdx.x * sa.gmu_stride : nullptr;
     const float thr = ip.tol2 * (float)C.E;
 
-    // held chunks k < KR of this wave: chunk wave + k W (a missing one repeats the
-    // wave's first chunk, whose lanes then take no part)
-    int hoff[KH];
-    bool hval[KH];
+    // held chunk h = j KH + k of this wave: chunk v + k W of plan wave v = wave + j NW
+    // (a missing one repeats the wave's first chunk, whose lanes then take no part)
+    int hoff[NHA];
+    bool hval[NHA];
 #pragma unroll
-    for (int k = 0; k < KH; ++k) {
-        const int c = wave + k * W;
-        const bool has = k < cpt && c < C.nchunks;
-        const ChunkDesc h = chunk_desc(C, has ? c : wave);
-        hoff[k] = h.off;
-        hval[k] = has && lane < h.cnt;
+    for (int h = 0; h < NHA; ++h) {
+        const int v = wave + (h / KH) * NW, k = h % KH;
+        const int c = v + k * W;
+        const bool has = v < W && k < cpt && c < C.nchunks;
+        const ChunkDesc cd = chunk_desc(C, has ? c : wave);
+        hoff[h] = cd.off;
+        hval[h] = has && lane < cd.cnt;
     }
-    float zr[PK ? 1 : KH][D], ur[PK ? 1 : KH][D];
-    unsigned hr[PK ? KH : 1][D];  // PK: z | u << 16 (FP16 bits) of held edge e of chunk k
+    float zr[PK ? 1 : NHA][D], ur[PK ? 1 : NHA][D];
+    unsigned hr[PK ? NHA : 1][D];  // PK: z | u << 16 (FP16 bits) of held edge e of chunk h
 
     int sbase = (int)blockIdx.x - kWave * (int)gridDim.x;
     unsigned long long smask = 0ull;
@@ -1596,7 +1605,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
         if constexpr (PERSIST) {
             const size_t fb0 = (size_t)f * C.E;
 #pragma unroll
-            for (int k = 0; k < KR; ++k)
+            for (int k = 0; k < NH; ++k)
 #pragma unroll
                 for (int e = 0; e < D; ++e) {
                     float z0 = 0.0f, u0 = 0.0f;
@@ -1679,8 +1688,8 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                 if constexpr (!PERSIST) load_held(0);
                 load_meta<D>(mcur, C.edge_meta, hoff[0], D, lane);
 #pragma unroll
-                for (int k = 0; k < KR; ++k) {
-                    if (k + 1 < KR) {
+                for (int k = 0; k < NH; ++k) {
+                    if (k + 1 < NH) {
                         if constexpr (!PERSIST) load_held(k + 1);
                         load_meta<D>(mnext, C.edge_meta, hoff[k + 1], D, lane);
                     }
@@ -1735,13 +1744,14 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
             }
         };
         // C: check updates (held chunks from registers, walked chunks from memory)
-        auto phase_c = [&](float &rp, float &rd) {
+        // residuals per plan wave: rp[j], rd[j] of plan wave wave + j NW
+        auto phase_c = [&](float *rp, float *rd) {
             if constexpr (KR > 0) {
                 uint32_t mcur[D], mnext[D];
                 load_meta<D>(mcur, C.edge_meta, hoff[0], D, lane);
 #pragma unroll
-                for (int k = 0; k < KR; ++k) {
-                    if (k + 1 < KR) load_meta<D>(mnext, C.edge_meta, hoff[k + 1], D, lane);
+                for (int k = 0; k < NH; ++k) {
+                    if (k + 1 < NH) load_meta<D>(mnext, C.edge_meta, hoff[k + 1], D, lane);
                     if constexpr (PK) {
                         if (hval[k]) {
                             float zz[D], uu[D];
@@ -1750,13 +1760,13 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                                 zz[e] = lo_h2f(hr[k][e]);
                                 uu[e] = hi_h2f(hr[k][e]);
                             }
-                            check_update<D, 2>(zz, uu, mcur, xs, ip.rho, rp, rd);
+                            check_update<D, 2>(zz, uu, mcur, xs, ip.rho, rp[k / KH], rd[k / KH]);
 #pragma unroll
                             for (int e = 0; e < D; ++e) hr[k][e] = pack_h2(zz[e], uu[e]);
                         }
                         __builtin_amdgcn_sched_barrier(0);
                     } else if (hval[k]) {
-                        check_update<D, 2>(zr[k], ur[k], mcur, xs, ip.rho, rp, rd);
+                        check_update<D, 2>(zr[k], ur[k], mcur, xs, ip.rho, rp[k / KH], rd[k / KH]);
                         if constexpr (!PERSIST) {
 #pragma unroll
                             for (int e = 0; e < D; ++e) {
@@ -1781,7 +1791,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                 uint32_t mn[D];
                 if (nxt.has) walk_load(nxt, zn, un, mn);
                 if (lane < cur.cnt) {
-                    check_update<D, 2>(zc, uc, mc, xs, ip.rho, rp, rd);
+                    check_update<D, 2>(zc, uc, mc, xs, ip.rho, rp[0], rd[0]);
 #pragma unroll
                     for (int e = 0; e < D; ++e) {
                         const size_t p = cur.off + e * kWave + lane;
@@ -1798,17 +1808,20 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                 cur = nxt;
             }
         };
-        auto publish = [&](int buf, float rp, float rd) {
-            rp = wave_sum(rp);
-            rd = wave_sum(rd);
-            if (lane == 0) {
-                s_red[buf][0][wave] = rp;
-                s_red[buf][1][wave] = rd;
+        auto publish = [&](int buf, const float *rp, const float *rd) {
+#pragma unroll
+            for (int j = 0; j < VW; ++j) {
+                const int v = wave + j * NW;  // wave-uniform
+                const float a = wave_sum(rp[j]), b = wave_sum(rd[j]);
+                if (lane == 0 && v < W) {
+                    s_red[buf][0][v] = a;
+                    s_red[buf][1][v] = b;
+                }
             }
         };
         auto converged = [&](int buf) -> bool {  // identical result in every wave
-            const float a = lane < NW ? s_red[buf][0][lane] : 0.0f;
-            const float b = lane < NW ? s_red[buf][1][lane] : 0.0f;
+            const float a = lane < W ? s_red[buf][0][lane] : 0.0f;
+            const float b = lane < W ? s_red[buf][1][lane] : 0.0f;
             return wave_sum(a) < thr && wave_sum(b) < thr;
         };
 
@@ -1824,7 +1837,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
             for (;; ++it) {
                 phase_b();
                 wg_barrier<true>();
-                float rp = 0.0f, rd = 0.0f;
+                float rp[VW] = {}, rd[VW] = {};
                 phase_c(rp, rd);
                 publish(it & 1, rp, rd);
                 wg_barrier<true>();
@@ -1843,7 +1856,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
             wg_barrier<true>();
             phase_b();
             wg_barrier<true>();
-            float rp = 0.0f, rd = 0.0f;
+            float rp[VW] = {}, rd[VW] = {};
             phase_c(rp, rd);
             publish(0, rp, rd);
             wg_barrier<true>();
@@ -1870,7 +1883,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
             frac = fmaxf(frac, fminf(x, 1.0f - x));
         }
         bool odd = false;
-        for (int c = wave; c < C.nchunks; c += W) {
+        for (int c = wave; c < C.nchunks; c += NW) {
             const ChunkDesc h = chunk_desc(C, c);
             if (lane < h.cnt) {
                 bool par = false;
@@ -1900,7 +1913,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
             if (sio.z_out) {
                 const size_t fb0 = (size_t)f * C.E;
 #pragma unroll
-                for (int k = 0; k < KR; ++k)
+                for (int k = 0; k < NH; ++k)
 #pragma unroll
                     for (int e = 0; e < D; ++e)
                         if (hval[k]) {
@@ -2099,10 +2112,11 @@ static hipError_t go_pair(const LaunchConfig &cfg, const DevCode *codes, const F
 }
 
 // large check-regular codes with the accumulator exchange (see k_decode_acc)
-template <int D, int KR, bool HALF, bool PERSIST>
+template <int D, int KR, bool HALF, bool PERSIST, int VW = 1>
 static hipError_t go_acc1(const LaunchConfig &cfg, const DevCode *codes, const FrameBatch &fb, const IterParams &ip,
                           const StateIO &sio, const StreamArgs &sa, hipStream_t stream, KernelQuery *q) {
-    auto kern = k_decode_acc<D, KR, HALF, PERSIST>;
+    if (cfg.threads > kMaxThreads / VW) return hipErrorInvalidConfiguration;
+    auto kern = k_decode_acc<D, KR, HALF, PERSIST, VW>;
     if (cfg.lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg.lds_bytes);
@@ -2132,6 +2146,9 @@ static hipError_t go_acc(const LaunchConfig &cfg, const DevCode *codes, const Fr
     }
 #define LPD_ACC_P(D, KR) \
     if (pg && !cfg.half && cfg.acc_d == D && cfg.acc_kr == KR) return go_acc1<D, KR, false, true>(cfg, codes, fb, ip, sio, sa, stream, q);
+// acc_kr = 2 kAccAllHeld: every chunk held, two plan waves per hardware wave
+#define LPD_ACC_P2(D) \
+    if (pg && !cfg.half && cfg.acc_d == D && cfg.acc_kr == 2 * kAccAllHeld) return go_acc1<D, kAccAllHeld, false, true, 2>(cfg, codes, fb, ip, sio, sa, stream, q);
 #define LPD_ACC_PH(D, KR) \
     if (pg && cfg.half && cfg.acc_d == D && cfg.acc_kr == KR) return go_acc1<D, KR, true, true>(cfg, codes, fb, ip, sio, sa, stream, q);
     if (cfg.form == Form::Resident) return hipErrorInvalidValue;
@@ -2143,6 +2160,7 @@ static hipError_t go_acc(const LaunchConfig &cfg, const DevCode *codes, const Fr
     LPD_ACC_P(6, 1)
     LPD_ACC_P(8, 0)
     LPD_ACC_P(8, 1)
+    LPD_ACC_P2(6)
     LPD_ACC_PH(6, 8)
     LPD_ACC_PH(6, 4)
     LPD_ACC_PH(8, 4)
@@ -2150,6 +2168,7 @@ static hipError_t go_acc(const LaunchConfig &cfg, const DevCode *codes, const Fr
 #undef LPD_ACC_S
 #undef LPD_ACC_P
 #undef LPD_ACC_PH
+#undef LPD_ACC_P2
     return hipErrorInvalidValue;
 }
 

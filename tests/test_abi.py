@@ -155,3 +155,12 @@ int main(){{ return !(check<2>(n2)&&check<3>(n3)&&check<4>(n4)&&check<5>(n5)&&ch
     exe = tmp_path / "net"
     subprocess.check_call(["g++", "-O1", "-o", str(exe), str(src)])
     assert subprocess.call([str(exe)]) == 0
+
+
+def test_binding_constants_match_the_header():
+    import re
+    hdr = open(os.path.join(ROOT, "include", "lpdec.h")).read()
+    py = open(os.path.join(ROOT, "paper_1204_0556_amd", "__init__.py")).read()
+    h = int(re.search(r"#define LPDEC_TUNE_VARIANTS (\d+)", hdr).group(1))
+    b = int(re.search(r"^TUNE_VARIANTS = (\d+)", py, re.M).group(1))
+    assert h == b == 4

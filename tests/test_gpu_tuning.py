@@ -74,7 +74,9 @@ def test_tuning_rejects_bad_values():
     with pytest.raises(lp.LpdecError):
         code.set_tuning(lp.MODE_RESIDENT, 33, -1)
     with pytest.raises(lp.LpdecError):
-        code.set_tuning(lp.MODE_STREAMED, 1, 3)
+        code.set_tuning(lp.MODE_STREAMED, 1, lp.TUNE_VARIANTS)
+    code.set_tuning(lp.MODE_STREAMED, 1, 3)  # a variant the form lacks falls back to the highest allowed
+    assert code.launch_info(mode=lp.MODE_STREAMED)["variant"] == 2
     code.set_tuning(lp.MODE_STREAMED, 1, 2)  # n = 96: staging allowed, default already
 
 
@@ -112,10 +114,15 @@ def test_large_code_held_chunk_variants_agree_bitwise(which):
     kw = dict(W.PAPER_PARAMS, max_iter=40)
     for mode, storage in ((lp.MODE_PERSISTENT_GLOBAL, 0), (lp.MODE_STREAMED, 0), (lp.MODE_STREAMED, 1)):
         ref = _decode(code, llr, mode, storage=storage, **kw)
-        for var in (0, 1, 2):
+        # persistent-global FP32, degree 6: variant 3 holds every chunk with two of the
+        # plan's waves per hardware wave (512 threads)
+        variants = (0, 1, 2, 3) if (mode == lp.MODE_PERSISTENT_GLOBAL and which == "36") else (0, 1, 2)
+        for var in variants:
             code.set_tuning(mode, 0, var)
             assert code.launch_info(mode=mode, storage=storage)["variant"] == var
             print(f"({which}) mode {mode} storage {storage} variant {var}", flush=True)
+            if var == 3:
+                assert code.launch_info(mode=mode, storage=storage)["threads"] == 512
             got = _decode(code, llr, mode, storage=storage, **kw)
             for a, b in zip(ref, got):
                 assert np.array_equal(a, b), (which, mode, storage, var)
