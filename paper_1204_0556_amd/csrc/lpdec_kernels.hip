@@ -380,6 +380,40 @@ __device__ __forceinline__ float from_fixed(unsigned long long a) {
     return (float)(long long)a * 0x1p-32f;
 }
 
+// Accumulator exchange, variable phase: x_i of variables tid, tid + NT, ... from
+// the variable's accumulator entry (less the previous x its high word still holds,
+// kept in xprev by the persistent forms; without xprev the high word is zero),
+// written back to the entry's high word and to xprev.  VBA variables per pass: their
+// global loads (previous x, gamma/mu, 1/degree) are issued together before the first
+// is used, so a pass waits once instead of once per variable.  PREV: xprev is given.
+template <int VBA, bool PREV>
+__device__ __forceinline__ void acc_x_update(unsigned long long *acc, unsigned *xprev, const float *gsrc,
+                                             float gscale, const DevCode &C, int tid, int NT) {
+    const auto vinv = as_global(reinterpret_cast<const int *>(C.var_info));
+    for (int i0 = tid; i0 < C.n; i0 += VBA * NT) {
+        unsigned prev[VBA];
+        float g[VBA], inv[VBA];
+#pragma unroll
+        for (int t = 0; t < VBA; ++t) {
+            const int i = i0 + t * NT;
+            const bool ok = i < C.n;
+            prev[t] = (PREV && ok) ? as_global(xprev)[i] : 0u;
+            g[t] = ok ? as_global(gsrc)[i] : 0.0f;
+            inv[t] = (C.dv > 0) ? C.dv_inv : (ok ? __int_as_float(vinv[2 * i + 1]) : 0.0f);
+        }
+#pragma unroll
+        for (int t = 0; t < VBA; ++t) {
+            const int i = i0 + t * NT;
+            if (i < C.n) {
+                const unsigned long long a = acc[i] - ((unsigned long long)prev[t] << 32);
+                const float x = clamp01((from_fixed(a) - g[t] * gscale) * inv[t]);
+                acc[i] = (unsigned long long)__float_as_uint(x) << 32;
+                if constexpr (PREV) as_global_rw(xprev)[i] = __float_as_uint(x);
+            }
+        }
+    }
+}
+
 // one check update of degree D on registers z,u (length DMAX arrays); x is read
 // from xs with stride XS (2 when x shares an accumulator entry)
 template <int D, int XS = 1>
@@ -806,17 +840,10 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                     if (i < C.n) xs[i] = x_update(slots, VarLoc{vslot[t], vdeg[t], vinv[t]}, vg[t]);
                 }
             } else if constexpr (SM == 2) {
-                const float *gsrc = C.var_identity ? gam : gmu_row;
-                const float gscale = C.var_identity ? ip.mu_inv : 1.0f;
-                for (int i = tid; i < C.n; i += NT) {
-                    const unsigned prev = xprev ? as_global(xprev)[i] : 0u;
-                    const unsigned long long a = acc[i] - ((unsigned long long)prev << 32);
-                    const float inv = (C.dv > 0) ? C.dv_inv
-                                                 : __int_as_float(as_global(reinterpret_cast<const int *>(C.var_info))[2 * i + 1]);
-                    const float x = clamp01((from_fixed(a) - gsrc[i] * gscale) * inv);
-                    acc[i] = (unsigned long long)__float_as_uint(x) << 32;
-                    if (xprev) as_global_rw(xprev)[i] = __float_as_uint(x);
-                }
+                // the persistent forms keep the previous x in xprev; the streamed form's
+                // entries start each launch with a zero high word
+                acc_x_update<4, PERSIST>(acc, xprev, C.var_identity ? gam : gmu_row,
+                                         C.var_identity ? ip.mu_inv : 1.0f, C, tid, NT);
             } else {
                 // gamma/mu: straight from the frame's LLRs when variables keep their
                 // order, else from the copy staged in internal order
@@ -1731,17 +1758,8 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
         };
         // B: x_i from its accumulator (less the previous x kept in the high word)
         auto phase_b = [&]() {
-            const float *gsrc = C.var_identity ? gam : gmu_row;
-            const float gscale = C.var_identity ? ip.mu_inv : 1.0f;
-            for (int i = tid; i < C.n; i += NT) {
-                const unsigned prev = PERSIST ? as_global(xprev)[i] : 0u;
-                const unsigned long long a = acc[i] - ((unsigned long long)prev << 32);
-                const float inv = (C.dv > 0) ? C.dv_inv
-                                             : __int_as_float(as_global(reinterpret_cast<const int *>(C.var_info))[2 * i + 1]);
-                const float x = clamp01((from_fixed(a) - as_global(gsrc)[i] * gscale) * inv);
-                acc[i] = (unsigned long long)__float_as_uint(x) << 32;
-                if constexpr (PERSIST) as_global_rw(xprev)[i] = __float_as_uint(x);
-            }
+            acc_x_update<4, PERSIST>(acc, xprev, C.var_identity ? gam : gmu_row, C.var_identity ? ip.mu_inv : 1.0f, C,
+                                     tid, NT);
         };
         // C: check updates (held chunks from registers, walked chunks from memory)
         // residuals per plan wave: rp[j], rd[j] of plan wave wave + j NW
