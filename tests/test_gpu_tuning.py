@@ -168,3 +168,19 @@ def test_fp16_persistent_global_needs_an_accumulator_code():
         lp.decode(code, llr, mode=lp.MODE_PERSISTENT_GLOBAL, storage=lp.STORAGE_FP16)
     with pytest.raises(lp.LpdecError):
         lp.decode(code, llr, mode=lp.MODE_RESIDENT, storage=lp.STORAGE_FP16)
+
+
+@pytest.mark.parametrize("which", ["36", "48"])
+def test_large_code_forms_agree_bitwise(which):
+    """n = 16384, FP32: the persistent-global default ((3,6): every chunk held, two of
+    the plan's waves per hardware wave; (4,8): one held chunk) and the streamed default
+    give bitwise the same x, iterations and flags."""
+    H = W.gallager36(16384) if which == "36" else W.gallager48(16384)
+    code = lp.Code(H)
+    llr = torch.from_numpy(np.concatenate([W.awgn_batch(H, 24, s, tag="forms-large") for s in (2.0, 2.5)])).cuda()
+    kw = dict(W.PAPER_PARAMS, max_iter=80)
+    pg = _decode(code, llr, lp.MODE_PERSISTENT_GLOBAL, **kw)
+    st = _decode(code, llr, lp.MODE_STREAMED, **kw)
+    print(f"({which}) forms: {code.launch_info(mode=lp.MODE_PERSISTENT_GLOBAL)}", flush=True)
+    for a, b in zip(pg, st):
+        assert np.array_equal(a, b), which
