@@ -61,6 +61,29 @@ def test_multi_code_frames_match_single_code_decodes_bitwise():
             assert it[f] == its[k] and fl[f] == fls[k]
 
 
+def test_multi_code_degree6_mid_size_matches_single_code_decodes_bitwise():
+    """(3,6) codes of n = 576, 2640 and 8064 in one launch: the fused launch runs the
+    resident kernel with four chunks per wave (sized for n = 8064), so the smaller codes'
+    frames go through a different kernel than when decoded alone (one or two chunks per
+    wave, or two frames per workgroup); the results are bitwise the same."""
+    codes = [W.gallager36(n) for n in (576, 2640, 8064)]
+    batch = W.mixed_batch(codes, 96, 1.5, 3.0, seed=4)
+    flat, off = batch.flat_llr()
+    handles = [lp.Code(H) for H in codes]
+    x, it, fl = lp.decode_multi(handles, batch.code_of_frame, off, dev(flat), off, flat.size)
+    x, it, fl = host(x), host(it), host(fl)
+    for c, H in enumerate(codes):
+        idx = np.nonzero(batch.code_of_frame == c)[0]
+        if idx.size == 0:
+            continue
+        llr = np.stack([batch.llr[f] for f in idx])
+        xs, its, fls = lp.decode(handles[c], dev(llr))
+        xs, its, fls = host(xs), host(its), host(fls)
+        for k, f in enumerate(idx):
+            assert np.array_equal(x[off[f]:off[f] + H.n], xs[k]), (H.n, f)
+            assert it[f] == its[k] and fl[f] == fls[k]
+
+
 def test_multi_code_against_oracle():
     codes, batch, flat, off = _mixed(96, seed=1)
     handles = [lp.Code(H) for H in codes]
