@@ -251,10 +251,15 @@ def workload_precision(args, lp, W, torch):
                 torch.cuda.synchronize()
                 ms = e0.elapsed_time(e1)
                 it_h = it.cpu().numpy().astype(np.int64)
+                ops = algorithmic_ops_per_frame_iter(H) * int(it_h.sum())
                 r = {"mbit_s": round(8192 * H.n / (ms / 1e3) / 1e6, 1), "ms": round(ms, 2),
                      "mean_iterations": round(float(it_h.mean()), 2),
                      "frame_errors": int(((x >= 0.5).any(dim=1)).sum().item()),
-                     "kernel_vgprs": code.launch_info(mode=mode, storage=st)["vgprs"]}
+                     "kernel_vgprs": code.launch_info(mode=mode, storage=st)["vgprs"],
+                     # the same algorithmic op count as the headline's VALU roofline (the
+                     # accumulator exchange's fixed-point conversions are not counted)
+                     "alu_tops": round(ops / (ms / 1e3) / 1e12, 2),
+                     "alu_frac": round(ops / (ms / 1e3) / 1e9 / VALU_PEAK_GOPS, 4)}
                 if mode == lp.MODE_STREAMED:
                     B = (16 if st == lp.STORAGE_FP32 else 8) * H.nnz + 4 * H.n
                     r.update({"bytes_per_frame_iter": B,
