@@ -217,19 +217,32 @@ _PRECISION = {}
 
 
 def _precision_full(which):
-    """The 8192-frame n = 16384 batch of the precision study in the launch the
-    benchmark times (streamed form), FP32 and FP16 storage, decoded once."""
+    """The 8192-frame n = 16384 batch of the precision study in the launches the
+    benchmark times, FP32 and FP16 storage, decoded once: the streamed form, and the
+    persistent-global form (which must give bitwise the same result on every frame)."""
     if which not in _PRECISION:
         H = W.gallager36(16384) if which == "36" else W.gallager48(16384)
         llr_h = W.awgn_batch(H, 8192, 2.5, tag="precision")
         code = lp.Code(H)
         print(f"precision batch ({which}) frames=8192", flush=True)
-        out = {}
+        out, out_pg = {}, {}
         for st in (lp.STORAGE_FP32, lp.STORAGE_FP16):
             x, it, fl = lp.decode(code, dev(llr_h), mode=lp.MODE_STREAMED, storage=st, **W.PAPER_PARAMS)
             out[st] = (host(x), host(it), host(fl))
-        _PRECISION[which] = (H, llr_h, out)
+            x, it, fl = lp.decode(code, dev(llr_h), mode=lp.MODE_PERSISTENT_GLOBAL, storage=st, **W.PAPER_PARAMS)
+            out_pg[st] = (host(x), host(it), host(fl))
+        _PRECISION[which] = (H, llr_h, out, out_pg)
     return _PRECISION[which]
+
+
+@pytest.mark.parametrize("which", ["36", "48"])
+def test_precision_batch_forms_agree_on_every_frame(which):
+    """Both storages: the persistent-global form (every chunk held in registers where
+    the registers allow it) equals the streamed form bitwise on all 8192 frames."""
+    _, _, out, out_pg = _precision_full(which)
+    for st in (lp.STORAGE_FP32, lp.STORAGE_FP16):
+        for a, b in zip(out[st], out_pg[st]):
+            assert np.array_equal(a, b), (which, st)
 
 
 @pytest.mark.parametrize("which,part", [("36", 0), ("48", 0), ("48", 1)])
@@ -237,7 +250,7 @@ def test_precision_batch_full_size(which, part):
     """Every frame of the precision batches in FP32 storage against the oracle (the
     (4,8) batch in two halves, to keep each test's oracle run short), and FP16 hard
     decisions against FP32 on every frame."""
-    H, llr_h, out = _precision_full(which)
+    H, llr_h, out, _ = _precision_full(which)
     sl = slice(0, 8192) if which == "36" else slice(part * 4096, (part + 1) * 4096)
     print(f"oracle on frames {sl.start}..{sl.stop} of ({which})", flush=True)
     ref = oracle.decode(H, llr_h[sl], **W.PAPER_PARAMS)
