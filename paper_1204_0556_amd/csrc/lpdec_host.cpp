@@ -218,8 +218,12 @@ lpdec_status build_plan(int32_t m, int32_t n, int64_t nnz, const int32_t *row_pt
     D.cpt = (D.nchunks + max_waves - 1) / max_waves;
     D.waves = (D.nchunks + D.cpt - 1) / D.cpt;
 
+    // accumulator exchange: each edge's entry as a byte offset (8 bytes per variable),
+    // so that the kernels address LDS without unpacking the metadata
+    std::vector<uint32_t> acc_off(meta.size());
+    for (size_t i = 0; i < meta.size(); ++i) acc_off[i] = 8u * (meta[i] & 0xffffu);
     int *d_cdeg, *d_coff, *d_ccnt, *d_ecsr, *d_vorig;
-    uint32_t *d_meta;
+    uint32_t *d_meta, *d_acc;
     int2 *d_vinfo;
     hipError_t e = hipGetDevice(&code->device);
     if (e != hipSuccess) return fail(LPDEC_EDEVICE, "no HIP device: %s", hipGetErrorString(e));
@@ -227,7 +231,8 @@ lpdec_status build_plan(int32_t m, int32_t n, int64_t nnz, const int32_t *row_pt
         (code->allocs.push_back(d_cdeg), (e = upload(chunk_off, &d_coff)) != hipSuccess) ||
         (code->allocs.push_back(d_coff), (e = upload(chunk_cnt, &d_ccnt)) != hipSuccess) ||
         (code->allocs.push_back(d_ccnt), (e = upload(meta, &d_meta)) != hipSuccess) ||
-        (code->allocs.push_back(d_meta), (e = upload(ecsr, &d_ecsr)) != hipSuccess) ||
+        (code->allocs.push_back(d_meta), (e = upload(acc_off, &d_acc)) != hipSuccess) ||
+        (code->allocs.push_back(d_acc), (e = upload(ecsr, &d_ecsr)) != hipSuccess) ||
         (code->allocs.push_back(d_ecsr), (e = upload(vorder, &d_vorig)) != hipSuccess) ||
         (code->allocs.push_back(d_vorig), (e = upload(vinfo, &d_vinfo)) != hipSuccess))
         return fail(e == hipErrorOutOfMemory ? LPDEC_ENOMEM : LPDEC_EDEVICE, "uploading the code: %s",
@@ -238,6 +243,7 @@ lpdec_status build_plan(int32_t m, int32_t n, int64_t nnz, const int32_t *row_pt
     D.chunk_off = d_coff;
     D.chunk_cnt = d_ccnt;
     D.edge_meta = d_meta;
+    D.edge_acc = d_acc;
     D.edge_csr = d_ecsr;
     D.var_orig = d_vorig;
     if ((e = hipMalloc(&code->d_dc, sizeof(DevCode))) != hipSuccess)

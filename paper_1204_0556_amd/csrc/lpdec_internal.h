@@ -60,6 +60,8 @@ struct DevCode {
     const int *chunk_off;     // [nchunks] offset into the lane-minor arrays
     const int *chunk_cnt;     // [nchunks] checks in the chunk (<= 64)
     const uint32_t *edge_meta;// [E_int] (slot << 16) | internal variable (0 on padding)
+    const uint32_t *edge_acc; // [E_int] 8 x internal variable: byte offset of the edge's
+                              // accumulator entry (the accumulator exchange's LDS address)
     const int *edge_csr;      // [E_int] CSR edge id (-1 on padding)
     const int *var_orig;      // [n] internal -> original variable index
     const int2 *var_info;     // [n] {slot0 | deg << 24, bits of 1/deg} per internal variable

@@ -380,6 +380,11 @@ __device__ __forceinline__ float from_fixed(unsigned long long a) {
     return (float)(long long)a * 0x1p-32f;
 }
 
+// The accumulator entry at byte offset off (edge_acc) of the accumulator array.
+__device__ __forceinline__ unsigned long long *acc_entry(unsigned long long *acc, uint32_t off) {
+    return reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(acc) + off);
+}
+
 // Accumulator exchange, variable phase: x_i of variables tid, tid + NT, ... from
 // the variable's accumulator entry (less the previous x its high word still holds,
 // kept in xprev by the persistent forms; without xprev the high word is zero),
@@ -416,13 +421,16 @@ __device__ __forceinline__ void acc_x_update(unsigned long long *acc, unsigned *
 
 // one check update of degree D on registers z,u (length DMAX arrays); x is read
 // from xs with stride XS (2 when x shares an accumulator entry)
-template <int D, int XS = 1>
+// (AB: meta holds the accumulator entries' byte offsets, from edge_acc; x then sits
+// at that offset from the accumulator array, i.e. at xs + offset - 4 bytes)
+template <int D, int XS = 1, bool AB = false>
 __device__ __forceinline__ void check_update(float *z, float *u, const uint32_t *meta, const float *xs,
                                              float rho, float &rp, float &rd) {
     float v[D], zn[D], xv[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        xv[k] = xs[XS * (meta[k] & 0xffffu)];
+        xv[k] = AB ? *reinterpret_cast<const float *>(reinterpret_cast<const char *>(xs) + meta[k])
+                   : xs[XS * (meta[k] & 0xffffu)];
         v[k] = fmaf(rho, xv[k] - z[k], z[k]) + u[k];  // q + u with q = rho x + (1-rho) z
     }
     project_pp<D>(v, zn);
@@ -798,11 +806,11 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                                 for (int e = 0; e < D; ++e) {
                                     const size_t p = h.off + e * kWave + lane;
                                     w[e] = ld_state<HALF>(gz, p) - ld_state<HALF>(gu, p);
-                                    mt[e] = as_global(C.edge_meta)[p];
+                                    mt[e] = as_global(SM == 2 ? C.edge_acc : C.edge_meta)[p];
                                 }
 #pragma unroll
                                 for (int e = 0; e < D; ++e) {
-                                    if constexpr (SM == 2) atomicAdd(acc + (mt[e] & 0xffffu), to_fixed(w[e]));
+                                    if constexpr (SM == 2) atomicAdd(acc_entry(acc, mt[e]), to_fixed(w[e]));
                                     else slots[mt[e] >> 16] = w[e];
                                 }
                             });
@@ -810,8 +818,8 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                             for (int e = 0; e < h.deg; ++e) {
                                 const size_t p = h.off + e * kWave + lane;
                                 const float w = ld_state<HALF>(gz, p) - ld_state<HALF>(gu, p);
-                                const uint32_t mt = as_global(C.edge_meta)[p];
-                                if constexpr (SM == 2) atomicAdd(acc + (mt & 0xffffu), to_fixed(w));
+                                const uint32_t mt = as_global(SM == 2 ? C.edge_acc : C.edge_meta)[p];
+                                if constexpr (SM == 2) atomicAdd(acc_entry(acc, mt), to_fixed(w));
                                 else slots[mt >> 16] = w;
                             }
                         }
@@ -987,9 +995,9 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                                 const size_t p = off + e * kWave + lane;
                                 zz[e] = ld_state<HALF>(gz, p);
                                 uu[e] = ld_state<HALF>(gu, p);
-                                mm[e] = as_global(C.edge_meta)[p];
+                                mm[e] = as_global(SM == 2 ? C.edge_acc : C.edge_meta)[p];
                             }
-                            check_update<D, XS>(zz, uu, mm, xs, ip.rho, rp, rd);
+                            check_update<D, XS, SM == 2>(zz, uu, mm, xs, ip.rho, rp, rd);
 #pragma unroll
                             for (int e = 0; e < D; ++e) {
                                 const size_t p = off + e * kWave + lane;
@@ -1704,7 +1712,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                 const size_t p = w.off + e * kWave + lane;
                 zz[e] = ld_state<HALF>(gz, p);
                 uu[e] = ld_state<HALF>(gu, p);
-                mm[e] = as_global(C.edge_meta)[p];
+                mm[e] = as_global(C.edge_acc)[p];
             }
         };
         auto phase_a = [&]() {
@@ -1713,18 +1721,18 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                 // k's accumulation waits for its own
                 uint32_t mcur[D], mnext[D];
                 if constexpr (!PERSIST) load_held(0);
-                load_meta<D>(mcur, C.edge_meta, hoff[0], D, lane);
+                load_meta<D>(mcur, C.edge_acc, hoff[0], D, lane);
 #pragma unroll
                 for (int k = 0; k < NH; ++k) {
                     if (k + 1 < NH) {
                         if constexpr (!PERSIST) load_held(k + 1);
-                        load_meta<D>(mnext, C.edge_meta, hoff[k + 1], D, lane);
+                        load_meta<D>(mnext, C.edge_acc, hoff[k + 1], D, lane);
                     }
                     if (hval[k]) {
 #pragma unroll
                         for (int e = 0; e < D; ++e) {
                             const float w = PK ? lo_h2f(hr[k][e]) - hi_h2f(hr[k][e]) : zr[PK ? 0 : k][e] - ur[PK ? 0 : k][e];
-                            atomicAdd(acc + (mcur[e] & 0xffffu), to_fixed(w));
+                            atomicAdd(acc_entry(acc, mcur[e]), to_fixed(w));
                         }
                     }
 #pragma unroll
@@ -1745,7 +1753,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                 if (nxt.has) walk_load(nxt, zn, un, mn);
                 if (lane < cur.cnt) {
 #pragma unroll
-                    for (int e = 0; e < D; ++e) atomicAdd(acc + (mc[e] & 0xffffu), to_fixed(zc[e] - uc[e]));
+                    for (int e = 0; e < D; ++e) atomicAdd(acc_entry(acc, mc[e]), to_fixed(zc[e] - uc[e]));
                 }
 #pragma unroll
                 for (int e = 0; e < D; ++e) {
@@ -1766,10 +1774,10 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
         auto phase_c = [&](float *rp, float *rd) {
             if constexpr (KR > 0) {
                 uint32_t mcur[D], mnext[D];
-                load_meta<D>(mcur, C.edge_meta, hoff[0], D, lane);
+                load_meta<D>(mcur, C.edge_acc, hoff[0], D, lane);
 #pragma unroll
                 for (int k = 0; k < NH; ++k) {
-                    if (k + 1 < NH) load_meta<D>(mnext, C.edge_meta, hoff[k + 1], D, lane);
+                    if (k + 1 < NH) load_meta<D>(mnext, C.edge_acc, hoff[k + 1], D, lane);
                     if constexpr (PK) {
                         if (hval[k]) {
                             float zz[D], uu[D];
@@ -1778,13 +1786,13 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                                 zz[e] = lo_h2f(hr[k][e]);
                                 uu[e] = hi_h2f(hr[k][e]);
                             }
-                            check_update<D, 2>(zz, uu, mcur, xs, ip.rho, rp[k / KH], rd[k / KH]);
+                            check_update<D, 2, true>(zz, uu, mcur, xs, ip.rho, rp[k / KH], rd[k / KH]);
 #pragma unroll
                             for (int e = 0; e < D; ++e) hr[k][e] = pack_h2(zz[e], uu[e]);
                         }
                         __builtin_amdgcn_sched_barrier(0);
                     } else if (hval[k]) {
-                        check_update<D, 2>(zr[k], ur[k], mcur, xs, ip.rho, rp[k / KH], rd[k / KH]);
+                        check_update<D, 2, true>(zr[k], ur[k], mcur, xs, ip.rho, rp[k / KH], rd[k / KH]);
                         if constexpr (!PERSIST) {
 #pragma unroll
                             for (int e = 0; e < D; ++e) {
@@ -1809,7 +1817,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                 uint32_t mn[D];
                 if (nxt.has) walk_load(nxt, zn, un, mn);
                 if (lane < cur.cnt) {
-                    check_update<D, 2>(zc, uc, mc, xs, ip.rho, rp[0], rd[0]);
+                    check_update<D, 2, true>(zc, uc, mc, xs, ip.rho, rp[0], rd[0]);
 #pragma unroll
                     for (int e = 0; e < D; ++e) {
                         const size_t p = cur.off + e * kWave + lane;
