@@ -38,8 +38,9 @@ extern "C" {
 #endif
 
 /* Largest check degree d = |N_c(j)| the kernels support (Sec. 2: the paper's
- * codes use d = 6 and d = 13; every workload here has d <= 8). */
-#define LPDEC_MAX_CHECK_DEGREE 8
+ * codes use d = 6 and d = 13).  Codes with a check of degree above 8 decode in
+ * the persistent-global and streamed forms only (not RESIDENT, not dual). */
+#define LPDEC_MAX_CHECK_DEGREE 16
 
 typedef enum {
     LPDEC_OK = 0,
@@ -215,7 +216,8 @@ lpdec_status lpdec_decode_multi(const lpdec_code *const *codes, int32_t ncodes, 
  * iterations.  x_out holds the last x (0 or 1 per bit).
  *   p  host; uses mu (step size, > 0) and max_iter; NULL = defaults
  * Other arguments as lpdec_decode.  LPDEC_EUNSUPPORTED when the code needs more
- * than 8 check chunks per wave (m > 8192) or 9 n bytes exceed the LDS. */
+ * than 8 check chunks per wave (m > 8192), has a check of degree above 8, or 9 n
+ * bytes exceed the LDS. */
 lpdec_status lpdec_decode_dual(const lpdec_code *code, int32_t batch, const float *llr,
                                const lpdec_params *p, float *x_out, int32_t *iters_out,
                                uint8_t *flags_out, void *stream);

@@ -35,7 +35,7 @@ STATE_IN, STATE_OUT = 0x1, 0x2
 EXECUTOR_GPU, EXECUTOR_HOST_NULL = 0, 1
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 EVAL_WORD_ERROR, EVAL_CODEWORD, EVAL_ML_ERROR = 0x01, 0x02, 0x04
-MAX_CHECK_DEGREE = 8
+MAX_CHECK_DEGREE = 16
 TUNE_VARIANTS = 4  # LPDEC_TUNE_VARIANTS
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED", -5: "EBUSY"}

@@ -49,6 +49,7 @@ lpdec_status lpdec_decode_dual(const lpdec_code *code, int32_t batch, const floa
         return fail(LPDEC_EINVAL, "llr, x_out, iters_out and flags_out must not be NULL");
     const DevCode &D = code->dc;
     if (D.cpt > 8) return fail(LPDEC_EUNSUPPORTED, "dual decoding holds at most 8 check chunks per wave");
+    if (D.dmax > 8) return fail(LPDEC_EUNSUPPORTED, "dual decoding supports check degrees up to 8 (code has %d)", D.dmax);
     DualLaunch L{};
     L.dclass = (D.dmin == 6 && D.dmax == 6) ? 0 : 1;
     L.cpt = D.cpt;

@@ -265,7 +265,7 @@ struct Shape {
 Shape shape_of(const lpdec_code *const *codes, int ncodes) {
     Shape s;
     s.ncodes = ncodes;
-    bool all6 = true, in68 = true;
+    bool all6 = true, in68 = true, upto8 = true;
     for (int c = 0; c < ncodes; ++c) {
         const DevCode &D = codes[c]->dc;
         s.nchunks = std::max(s.nchunks, D.nchunks);
@@ -276,9 +276,10 @@ Shape shape_of(const lpdec_code *const *codes, int ncodes) {
         s.Eint_max = std::max(s.Eint_max, D.E_int);
         all6 = all6 && D.dmin == 6 && D.dmax == 6;
         in68 = in68 && D.dmin >= 6 && D.dmax <= 8;
+        upto8 = upto8 && D.dmax <= 8;
         s.permuted = s.permuted || !D.var_identity;
     }
-    s.dclass = all6 ? 0 : (in68 ? 2 : 1);
+    s.dclass = all6 ? 0 : (in68 ? 2 : (upto8 ? 1 : 3));
     s.dv = (codes[0]->dc.nvc == 1) ? codes[0]->dc.vc_deg[0] : 0;
     for (int c = 1; c < ncodes; ++c)
         if (codes[c]->dc.nvc != 1 || codes[c]->dc.vc_deg[0] != s.dv) s.dv = 0;
@@ -485,7 +486,7 @@ bool persistent_global_config(const Shape &s, LaunchConfig *cfg, int variant = -
     cfg->form = Form::PersistentGlobal;
     cfg->cpt_tmpl = 0;
     cfg->vpt_tmpl = 0;
-    cfg->dclass = s.dclass == 0 ? 0 : 1;
+    cfg->dclass = s.dclass == 2 ? 1 : s.dclass;
     cfg->dv = 0;
     cfg->slot_mode = slot_mode_for(s, &cfg->lds_bytes);
     cfg->half = half;
@@ -509,7 +510,7 @@ void streamed_config(const Shape &s, bool half, LaunchConfig *cfg, int variant =
     cfg->form = Form::Streamed;
     cfg->slot_mode = slot_mode_for(s, &cfg->lds_bytes);
     cfg->cpt_tmpl = (cfg->slot_mode == 1 && s.cpt <= 2 && s.dclass == 0) ? 2 : 0;
-    cfg->dclass = s.dclass == 0 ? 0 : 1;
+    cfg->dclass = s.dclass == 2 ? 1 : s.dclass;
     const int threads = s.waves * kWave;
     // staged: all LDS static (z, u, slots of kStageEdges; gamma/mu, x of kStageVars)
     const size_t stage_lds = sizeof(float) * (3 * (size_t)kStageEdges + 2 * kStageVars);

@@ -13,7 +13,7 @@ constexpr int kMaxWaves = kMaxThreads / kWave;
 // LDS staging of the streamed form: one frame's z, u (edges) and gamma/mu (variables)
 constexpr int kStageEdges = 8192;
 constexpr int kStageVars = 4096;
-constexpr int kMaxD = 8;           // LPDEC_MAX_CHECK_DEGREE
+constexpr int kMaxD = 16;          // LPDEC_MAX_CHECK_DEGREE
 constexpr int kAccAllHeld = 8;     // k_decode_acc: held chunks per wave that compile the chunk walk out
 
 // A pointer read from memory (a code table, an argument structure) is generic to
@@ -124,7 +124,8 @@ struct LaunchConfig {
     Form form;
     int cpt_tmpl;      // register-held chunks per wave: 0 (re-read), 2 or 4
     int vpt_tmpl;      // register-held variables per thread (resident form): 4 or 8
-    int dclass;        // 0: degrees exactly 6; 1: degrees 2..8; 2: degrees 6..8 (resident form)
+    int dclass;        // 0: degrees exactly 6; 1: degrees 2..8; 2: degrees 6..8 (resident form);
+                       // 3: degrees 2..16 (persistent-global and streamed forms)
     int dv;            // every variable has this degree (0: mixed), resident form
     int slot_mode;     // 0 global float slots, 1 LDS float slots, 2 LDS fixed-point accumulators
     bool half;         // fp16 state storage (streamed only)

@@ -75,6 +75,14 @@ __device__ __forceinline__ void sort_desc(float *s) {
     else if constexpr (D == 6) { LPD_NET_6 }
     else if constexpr (D == 7) { LPD_NET_7 }
     else if constexpr (D == 8) { LPD_NET_8 }
+    else if constexpr (D == 9) { LPD_NET_9 }
+    else if constexpr (D == 10) { LPD_NET_10 }
+    else if constexpr (D == 11) { LPD_NET_11 }
+    else if constexpr (D == 12) { LPD_NET_12 }
+    else if constexpr (D == 13) { LPD_NET_13 }
+    else if constexpr (D == 14) { LPD_NET_14 }
+    else if constexpr (D == 15) { LPD_NET_15 }
+    else if constexpr (D == 16) { LPD_NET_16 }
 }
 #undef LPD_CE
 
@@ -132,7 +140,7 @@ __device__ __forceinline__ void project_pp(const float *v, float *z) {
     const bool all_top = (rf + 1.0f >= (float)D);
     if (!all_top && !(t1 > t2)) return;  // beta_max = 0
     const float beta_max = all_top ? t1 : 0.5f * (t1 - t2);
-    constexpr int P = (D <= 2) ? 2 : ((D <= 4) ? 4 : 8);
+    constexpr int P = (D <= 2) ? 2 : ((D <= 4) ? 4 : ((D <= 8) ? 8 : 16));
     float bp[P];
 #pragma unroll
     for (int k = 0; k < P; ++k)
@@ -175,6 +183,14 @@ hipError_t launch_project(int d, int count, const float *v, float *z, hipStream_
         case 6: hipLaunchKernelGGL(k_project<6>, grid, block, 0, stream, count, v, z); break;
         case 7: hipLaunchKernelGGL(k_project<7>, grid, block, 0, stream, count, v, z); break;
         case 8: hipLaunchKernelGGL(k_project<8>, grid, block, 0, stream, count, v, z); break;
+        case 9: hipLaunchKernelGGL(k_project<9>, grid, block, 0, stream, count, v, z); break;
+        case 10: hipLaunchKernelGGL(k_project<10>, grid, block, 0, stream, count, v, z); break;
+        case 11: hipLaunchKernelGGL(k_project<11>, grid, block, 0, stream, count, v, z); break;
+        case 12: hipLaunchKernelGGL(k_project<12>, grid, block, 0, stream, count, v, z); break;
+        case 13: hipLaunchKernelGGL(k_project<13>, grid, block, 0, stream, count, v, z); break;
+        case 14: hipLaunchKernelGGL(k_project<14>, grid, block, 0, stream, count, v, z); break;
+        case 15: hipLaunchKernelGGL(k_project<15>, grid, block, 0, stream, count, v, z); break;
+        case 16: hipLaunchKernelGGL(k_project<16>, grid, block, 0, stream, count, v, z); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2079,6 +2095,32 @@ static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const 
         default:
             // degrees 6..8 are built for the resident form only
             if constexpr (!(DMIN == 6 && DMAX == 8)) {
+                // checks above degree 8: the per-check arrays need more than the 128
+                // registers a lane has at 16 waves, so codes of at most 8 waves get a
+                // build for 512 threads (256 registers)
+                if constexpr (DMAX > 8) {
+                    if (cfg.threads <= 512) {
+                        switch (cfg.form) {
+                            case Form::PersistentGlobal:
+                                if (cfg.slot_mode == 1) LPD_GO(0, 0, false, true, 1, false, 512);
+                                if (cfg.slot_mode == 2) LPD_GO(0, 0, false, true, 2, false, 512);
+                                LPD_GO(0, 0, false, true, 0, false, 512);
+                            case Form::Streamed:
+                                if (cfg.slot_mode == 1) {
+                                    if (!cfg.half) LPD_GO(0, 0, false, false, 1, false, 512);
+                                    LPD_GO(0, 0, false, false, 1, true, 512);
+                                }
+                                if (cfg.slot_mode == 2) {
+                                    if (!cfg.half) LPD_GO(0, 0, false, false, 2, false, 512);
+                                    LPD_GO(0, 0, false, false, 2, true, 512);
+                                }
+                                if (!cfg.half) LPD_GO(0, 0, false, false, 0, false, 512);
+                                LPD_GO(0, 0, false, false, 0, true, 512);
+                            default:
+                                break;
+                        }
+                    }
+                }
                 switch (cfg.form) {
                     case Form::PersistentGlobal:
                         if (cfg.slot_mode == 1) LPD_GO(0, 0, false, true, 1, false);
@@ -2204,6 +2246,7 @@ hipError_t launch_decode(const LaunchConfig &cfg, const DevCode *codes_dev, cons
     if (cfg.acc) return go_acc(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
     if (cfg.dclass == 0) return go_range<6, 6>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
     if (cfg.dclass == 2) return go_range<6, 8>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
+    if (cfg.dclass == 3) return go_range<2, kMaxD>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
     return go_range<2, 8>(cfg, codes_dev, fb, ip, sio, sa, stream, nullptr);
 }
 
@@ -2217,6 +2260,7 @@ hipError_t decode_query(const LaunchConfig &cfg, KernelQuery *q) {
     if (cfg.acc) return go_acc(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
     if (cfg.dclass == 0) return go_range<6, 6>(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
     if (cfg.dclass == 2) return go_range<6, 8>(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
+    if (cfg.dclass == 3) return go_range<2, kMaxD>(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
     return go_range<2, 8>(cfg, nullptr, fb, ip, sio, sa, nullptr, q);
 }
 

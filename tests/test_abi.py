@@ -66,7 +66,7 @@ def _create(lib, m, n, row_ptr, col_idx):
     ("unsorted row", 1, 3, [0, 3], [2, 0, 1], EINVAL, "strictly increasing"),
     ("index out of range", 1, 3, [0, 3], [0, 1, 3], EINVAL, "out of range"),
     ("bad row_ptr end", 1, 3, [0, 2], [0, 1, 2], EINVAL, "nnz"),
-    ("degree above max", 1, 9, [0, 9], list(range(9)), EUNSUPPORTED, "degree 9"),
+    ("degree above max", 1, 17, [0, 17], list(range(17)), EUNSUPPORTED, "degree 17"),
     ("no rows", 0, 3, [0], [0], EINVAL, "m and n"),
     # size limits: 16-bit variable and slot indices in the edge metadata
     ("n too large", 1, 65537, [0, 2], [0, 1], EUNSUPPORTED, "n > 65536"),
@@ -92,7 +92,7 @@ def test_null_arguments(lib):
 
 def test_project_argument_checks(lib):
     lib.lpdec_project.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
-    assert lib.lpdec_project(9, 4, None, None, None) == EINVAL
+    assert lib.lpdec_project(17, 4, None, None, None) == EINVAL
     assert lib.lpdec_project(1, 4, None, None, None) == EINVAL
     assert lib.lpdec_project(6, -1, None, None, None) == EINVAL
     assert lib.lpdec_project(6, 0, None, None, None) == 0  # empty batch is a no-op
@@ -145,12 +145,16 @@ def test_sorting_networks_sort_every_binary_input(tmp_path):
 #define LPD_CE(a,b) {{ int p=s[a], q=s[b]; s[a]=p>q?p:q; s[b]=p>q?q:p; }}
 #include "{inc}"
 template <int D> int check(void (*f)(int*)) {{
-  for (int m = 0; m < (1 << D); ++m) {{ int s[8]; for (int k = 0; k < D; ++k) s[k] = (m >> k) & 1; f(s);
+  for (int m = 0; m < (1 << D); ++m) {{ int s[16]; for (int k = 0; k < D; ++k) s[k] = (m >> k) & 1; f(s);
     for (int k = 1; k < D; ++k) if (s[k-1] < s[k]) return 0; }}
   return 1; }}
 void n2(int*s){{LPD_NET_2}} void n3(int*s){{LPD_NET_3}} void n4(int*s){{LPD_NET_4}} void n5(int*s){{LPD_NET_5}}
 void n6(int*s){{LPD_NET_6}} void n7(int*s){{LPD_NET_7}} void n8(int*s){{LPD_NET_8}}
-int main(){{ return !(check<2>(n2)&&check<3>(n3)&&check<4>(n4)&&check<5>(n5)&&check<6>(n6)&&check<7>(n7)&&check<8>(n8)); }}
+void n9(int*s){{LPD_NET_9}} void n10(int*s){{LPD_NET_10}} void n11(int*s){{LPD_NET_11}} void n12(int*s){{LPD_NET_12}}
+void n13(int*s){{LPD_NET_13}} void n14(int*s){{LPD_NET_14}} void n15(int*s){{LPD_NET_15}} void n16(int*s){{LPD_NET_16}}
+int main(){{ return !(check<2>(n2)&&check<3>(n3)&&check<4>(n4)&&check<5>(n5)&&check<6>(n6)&&check<7>(n7)&&check<8>(n8)
+  &&check<9>(n9)&&check<10>(n10)&&check<11>(n11)&&check<12>(n12)&&check<13>(n13)&&check<14>(n14)
+  &&check<15>(n15)&&check<16>(n16)); }}
 ''')
     exe = tmp_path / "net"
     subprocess.check_call(["g++", "-O1", "-o", str(exe), str(src)])

@@ -56,7 +56,7 @@ def _proj_inputs(d, count, seed):
     return np.concatenate(parts).astype(np.float32)
 
 
-@pytest.mark.parametrize("d", [2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("d", list(range(2, 17)))
 def test_projection_matches_oracle(d):
     v = _proj_inputs(d, 2000, 1)
     print(f"projection d={d} count={len(v)}", flush=True)

@@ -41,7 +41,7 @@ def _random_inputs(d, count, seed):
     return out
 
 
-@pytest.mark.parametrize("d", [2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("d", [2, 3, 4, 5, 6, 7, 8, 10, 13, 16])
 def test_projection_equals_brute_force_vertex_qp(d):
     for v in _random_inputs(d, 60, seed=1):
         z = oracle.project(v)
@@ -49,7 +49,7 @@ def test_projection_equals_brute_force_vertex_qp(d):
         assert np.max(np.abs(z - zb)) < 1e-9, (v, z, zb)
 
 
-@pytest.mark.parametrize("d", [3, 6, 8])
+@pytest.mark.parametrize("d", [3, 6, 8, 13])
 def test_projection_variational_certificate(d):
     # z = Pi_C(v) iff z in C and <v - z, e - z> <= 0 for every vertex e of C.
     for v in _random_inputs(d, 30, seed=2):

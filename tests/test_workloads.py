@@ -34,6 +34,21 @@ def test_irregular_codes(n):
     assert len(H.four_cycle_pairs()) == 0
 
 
+@pytest.mark.parametrize("n", [1057, 16380])
+def test_code313(n):
+    # n = 1057: the [1057,813] shape (m = 244 independent checks, 243 of degree 13
+    # and one of degree 12); 13 | 16380 gives an exactly (3,13)-regular code
+    H = W.code313(n)
+    assert np.all(H.var_degrees() == 3) and H.nnz == 3 * n
+    cd = np.bincount(H.check_degrees(), minlength=14)
+    if n == 1057:
+        assert H.m == 244 and cd[13] == 243 and cd[12] == 1
+        assert n - W.gf2_rank(H) == 813
+    else:
+        assert H.m == 3 * n // 13 and cd[13] == H.m
+    assert len(H.four_cycle_pairs()) == 0
+
+
 def test_codes_are_deterministic():
     a, b = W.gallager_regular(96, 3, 6, seed=5), W.gallager_regular(96, 3, 6, seed=5)
     assert np.array_equal(a.col_idx, b.col_idx)

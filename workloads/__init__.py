@@ -22,7 +22,7 @@ __all__ = [
     "awgn_llr", "bsc_llr", "sigma2_for", "PAPER_PARAMS", "gallager36", "gallager48",
     "irregular_half", "IRREGULAR_LENGTHS", "Batch", "awgn_batch", "mixed_batch",
     "HEADLINE_SNRS", "serving_trace", "SERVING_LENGTHS", "random_regular", "bsc_ensemble",
-    "bsc_batch", "BSC_CROSSOVERS", "BSC_ENSEMBLE_SIZE",
+    "bsc_batch", "BSC_CROSSOVERS", "BSC_ENSEMBLE_SIZE", "code313",
 ]
 
 # Decoder parameters used for every simulation of Sec. 5.1: eps = 1e-5, mu = 3,
@@ -52,6 +52,18 @@ def gallager36(n: int) -> ParityCheckMatrix:
 def gallager48(n: int) -> ParityCheckMatrix:
     """(4,8)-regular Gallager code of length n (fixed seed per n)."""
     return gallager_regular(n, 4, 8, seed=n)
+
+
+@functools.lru_cache(maxsize=None)
+def code313(n: int = 1057) -> ParityCheckMatrix:
+    """Variable degree 3, check degree 13: the stand-in for the paper's [1057,813] code
+    (n = 1057: 3 n = 3171 edges over m = 244 checks, so 243 checks of degree 13 and one
+    of degree 12; H then has full rank, dimension 813).  For 13 | n every check has
+    degree 13 (m = 3 n / 13)."""
+    m = -(-3 * n // 13)
+    short = 13 * m - 3 * n  # checks of degree 12
+    chk = {13: (m - short) / m} if short == 0 else {12: short / m, 13: (m - short) / m}
+    return irregular(n, {3: 1.0}, chk, m=m, seed=n)
 
 
 @functools.lru_cache(maxsize=None)
@@ -90,10 +102,12 @@ class Batch:
         return np.concatenate(self.llr).astype(np.float32), off
 
 
-def awgn_batch(H: ParityCheckMatrix, frames: int, ebn0_db: float, tag: str = "awgn", block: int = 0) -> np.ndarray:
-    """[frames, n] float32 gamma for one code at one Eb/N0 (seeded by code length, SNR and block)."""
+def awgn_batch(H: ParityCheckMatrix, frames: int, ebn0_db: float, tag: str = "awgn", block: int = 0,
+               rate: float = 0.5) -> np.ndarray:
+    """[frames, n] float32 gamma for one code at one Eb/N0 (seeded by code length, SNR and block);
+    `rate` is the code rate the noise level is computed for (1/2 for the rate-1/2 codes)."""
     rng = rng_for(tag, H.n, H.m, int(round(ebn0_db * 1000)), block)
-    return awgn_llr(H.n, frames, ebn0_db, rng)
+    return awgn_llr(H.n, frames, ebn0_db, rng, rate=rate)
 
 
 def bsc_batch(H: ParityCheckMatrix, frames: int, p: float, tag: str = "bsc", block: int = 0) -> np.ndarray:
