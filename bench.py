@@ -31,6 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # Non-packed FP32 VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 VALU_PEAK_GOPS = 256 * 64 * 2.4
 FRAMES_PER_SNR = 4096
+CODE313_SNRS = (3.0, 3.5, 4.0, 4.5)
 
 
 def algorithmic_bytes_per_frame_iter(H) -> int:
@@ -47,8 +48,10 @@ def algorithmic_ops_per_frame_iter(H) -> int:
                  network of S_d comparators, f_r^T zhat, thresholds, breakpoints,
                  bitonic merge of M_d comparators, prefix averages, final clip)
       per variable  d_v + 3  (slot sum, gamma/mu, scale, clip)"""
-    S = {2: 1, 3: 3, 4: 5, 5: 9, 6: 12, 7: 16, 8: 19}
+    S = {2: 1, 3: 3, 4: 5, 5: 9, 6: 12, 7: 16, 8: 19, 9: 28, 10: 32, 11: 38, 12: 42, 13: 48, 14: 53, 15: 59,
+         16: 63}
     M = {2: 1, 3: 4, 4: 4, 5: 12, 6: 12, 7: 12, 8: 12}
+    M.update({d: 32 for d in range(9, 17)})
     cd = H.check_degrees()
     vd = H.var_degrees()
     ops = 9 * H.nnz
@@ -466,6 +469,56 @@ def workload_bsc(args, lp, W, torch):
     }
 
 
+def workload_code313(args, lp, W, torch):
+    """The (3,13) code class of Sec. 5 (stand-in for the [1057,813] code: 243 checks of
+    degree 13, one of 12): `--sweep-frames` frames at each Eb/N0 in CODE313_SNRS (noise for
+    the code's rate 813/1057), the paper's parameters, decoded in one batch by the default
+    form (persistent-global; checks above degree 8 have no resident form) and, for
+    comparison, the streamed form.  Reports throughput, WER per Eb/N0 and the VALU roofline
+    of the default form."""
+    H = W.code313(1057)
+    rate = 1.0 - H.m / H.n
+    F = args.sweep_frames
+    P = W.PAPER_PARAMS
+    llr_h = np.concatenate([W.awgn_batch(H, F, s, tag="code313-bench", rate=rate) for s in CODE313_SNRS])
+    llr = torch.from_numpy(llr_h).cuda()
+    code = lp.Code(H)
+    li = code.launch_info()
+    (x, it, fl), ms = _timed(torch, lambda: lp.decode(code, llr, **P), steps=args.steps, warmup=args.warmup)
+    (xs, its, fls), ms_s = _timed(torch, lambda: lp.decode(code, llr, mode=lp.MODE_STREAMED, **P),
+                                  steps=args.steps, warmup=args.warmup)
+    torch.cuda.synchronize()
+    x_h, it_h, fl_h = x.cpu().numpy(), it.cpu().numpy(), fl.cpu().numpy()
+    same = bool(np.array_equal(x_h, xs.cpu().numpy()) and np.array_equal(it_h, its.cpu().numpy())
+                and np.array_equal(fl_h, fls.cpu().numpy()))
+    werr = (x_h >= 0.5).any(axis=1)
+    per_snr = {}
+    for b, snr in enumerate(CODE313_SNRS):
+        sl = slice(b * F, (b + 1) * F)
+        k = int(werr[sl].sum())
+        per_snr[str(snr)] = {"frames": F, "word_errors": k, "wer": k / F, "wer_ci95": _clopper_pearson(k, F),
+                             "iterations": _iteration_stats(it_h[sl], werr[sl]),
+                             "certified": int(((fl_h[sl] & lp.FLAG_CERTIFIED) != 0).sum())}
+    frames = llr_h.shape[0]
+    ops = algorithmic_ops_per_frame_iter(H) * int(it_h.astype(np.int64).sum())
+    achieved = ops / (ms / 1e3) / 1e9
+    return {
+        "metric": METRIC, "value": round(frames * H.n / (ms / 1e3) / 1e6, 2), "unit": "Mbit/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"(3,13) code class: variable degree 3, n={H.n}, m={H.m} (243 checks of degree 13, "
+                               f"one of 12, rate {rate:.4f}), {F} frames at each Eb/N0 in {list(CODE313_SNRS)} dB, "
+                               "all-zero codeword over BPSK/AWGN, mu=3 rho=1.9 max_iter=1000 tol=1e-5, one batch"},
+        "launch": li,
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e3, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 2),
+                     "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_GOPS, 4), "traffic": None,
+                     "kernel": "k_decode (persistent-global, check degrees 2..16)"},
+        "streamed": {"ms": round(ms_s, 3), "mbit_s": round(frames * H.n / (ms_s / 1e3) / 1e6, 2),
+                     "bitwise_equal_to_default_form": same},
+        "per_ebn0": per_snr,
+    }
+
+
 def workload_sweep(args, lp, W, torch):
     """Parameter sensitivity of Sec. 5.2 on the (3,6) n = 2640 code: WER and decode time
     against the stopping tolerance (2.2 dB, mu in {1,5,7}, rho = 1), against mu
@@ -571,7 +624,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the plain and streamed comparisons and the per-Eb/N0 blocks decoded alone")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "uneven", "precision", "serving", "bsc", "sweep", "dual", "streamed_large"])
+                    choices=["headline", "uneven", "precision", "serving", "bsc", "sweep", "dual", "streamed_large",
+                             "code313"])
     ap.add_argument("--bsc-frames", type=int, default=128, help="frames per code and crossover (bsc workload)")
     ap.add_argument("--sweep-frames", type=int, default=4096, help="frames per point (sweep and dual workloads)")
     ap.add_argument("--serving-seconds", type=float, default=1.0,
@@ -621,6 +675,9 @@ def main():
         return
     if args.workload == "streamed_large":
         print(json.dumps(workload_streamed_large(args, lp, W, torch)))
+        return
+    if args.workload == "code313":
+        print(json.dumps(workload_code313(args, lp, W, torch)))
         return
 
     modes = {"auto": lp.MODE_AUTO, "resident": lp.MODE_RESIDENT,

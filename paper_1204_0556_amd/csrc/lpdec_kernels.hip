@@ -2095,32 +2095,10 @@ static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const 
         default:
             // degrees 6..8 are built for the resident form only
             if constexpr (!(DMIN == 6 && DMAX == 8)) {
-                // checks above degree 8: the per-check arrays need more than the 128
-                // registers a lane has at 16 waves, so codes of at most 8 waves get a
-                // build for 512 threads (256 registers)
-                if constexpr (DMAX > 8) {
-                    if (cfg.threads <= 512) {
-                        switch (cfg.form) {
-                            case Form::PersistentGlobal:
-                                if (cfg.slot_mode == 1) LPD_GO(0, 0, false, true, 1, false, 512);
-                                if (cfg.slot_mode == 2) LPD_GO(0, 0, false, true, 2, false, 512);
-                                LPD_GO(0, 0, false, true, 0, false, 512);
-                            case Form::Streamed:
-                                if (cfg.slot_mode == 1) {
-                                    if (!cfg.half) LPD_GO(0, 0, false, false, 1, false, 512);
-                                    LPD_GO(0, 0, false, false, 1, true, 512);
-                                }
-                                if (cfg.slot_mode == 2) {
-                                    if (!cfg.half) LPD_GO(0, 0, false, false, 2, false, 512);
-                                    LPD_GO(0, 0, false, false, 2, true, 512);
-                                }
-                                if (!cfg.half) LPD_GO(0, 0, false, false, 0, false, 512);
-                                LPD_GO(0, 0, false, false, 0, true, 512);
-                            default:
-                                break;
-                        }
-                    }
-                }
+                // checks above degree 8 use the same builds: their per-check arrays spill
+                // 15-27 registers at the 128 a lane has here, but a build for 512 threads
+                // (167 registers, no spills) ran the (3,13) n = 1057 code 1.37x slower in
+                // the persistent-global form at two workgroups per CU instead of three
                 switch (cfg.form) {
                     case Form::PersistentGlobal:
                         if (cfg.slot_mode == 1) LPD_GO(0, 0, false, true, 1, false);
