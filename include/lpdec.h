@@ -39,7 +39,8 @@ extern "C" {
 
 /* Largest check degree d = |N_c(j)| the kernels support (Sec. 2: the paper's
  * codes use d = 6 and d = 13).  Codes with a check of degree above 8 decode in
- * the persistent-global and streamed forms only (not RESIDENT, not dual). */
+ * the persistent-global and streamed forms, in RESIDENT only with one chunk of
+ * checks per wave (at most 1024 checks), and not in the dual decoder. */
 #define LPDEC_MAX_CHECK_DEGREE 16
 
 typedef enum {
@@ -72,7 +73,9 @@ typedef enum {
 #define LPDEC_MODE_RESIDENT 1 /* one persistent launch; a workgroup keeps a frame's
                                  replicas and duals in registers until it converges
                                  (codes whose checks all have degree 6, or all degrees
-                                 6..8, and whose state fits; see resident_capable)     */
+                                 6..8, and whose state fits, and codes with a check
+                                 above degree 8 that need one chunk of 64 checks per
+                                 wave, m <= 1024; see resident_capable)               */
 #define LPDEC_MODE_STREAMED 2 /* replicas and duals live in HBM; one launch per
                                  iteration over all unfinished frames                  */
 #define LPDEC_MODE_PERSISTENT_GLOBAL 3 /* one persistent launch; per-workgroup state in
@@ -195,8 +198,8 @@ lpdec_status lpdec_decode_noalloc(const lpdec_code *code, int32_t batch, const f
  * not depend on the other frames of the batch.  When the codes differ in size,
  * the launch hands out frames of larger codes first (processing order only).
  * AUTO picks the register-resident form when every code's checks have degree 6
- * (or all lie in 6..8) and the largest code fits its register and LDS budget,
- * else the persistent-global form.  FP16 storage and the streamed form are not
+ * (or all lie in 6..8, or the codes need one chunk per wave) and the largest code
+ * fits its register and LDS budget, else the persistent-global form.  FP16 storage and the streamed form are not
  * available here (LPDEC_EUNSUPPORTED). */
 lpdec_status lpdec_decode_multi(const lpdec_code *const *codes, int32_t ncodes, int32_t nframes,
                                 const int32_t *code_of_frame, const int64_t *llr_offset,

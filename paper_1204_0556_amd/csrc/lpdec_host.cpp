@@ -369,6 +369,24 @@ bool resident_config(const Shape &s, LaunchConfig *cfg, int variant = -1) {
         cfg->state_stride = 0;
         return true;
     }
+    if (s.dclass == 3) {
+        // checks above degree 8: one chunk per wave, its z and u in registers
+        const size_t lds = 4 * ((size_t)s.Emax + s.nmax);
+        if (s.cpt > 1 || lds + kStaticLds > kLdsLimit) return false;
+        cfg->form = Form::Resident;
+        cfg->cpt_tmpl = 1;
+        cfg->vpt_tmpl = 0;
+        cfg->dclass = 3;
+        cfg->dv = 0;
+        cfg->slot_mode = 1;
+        cfg->half = false;
+        cfg->threads = s.waves * kWave;
+        cfg->lds_bytes = lds;
+        cfg->lds_E = s.Emax;
+        cfg->slot_stride = 0;
+        cfg->state_stride = 0;
+        return true;
+    }
     if (s.dclass != 0) return false;  // register budget only holds for degree-6 codes
     if (s.cpt > 4) return false;
     const int threads = s.waves * kWave;

@@ -2085,6 +2085,10 @@ static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const 
             // checks of degree 6..8: z, u of up to eight chunks per wave in registers,
             // variables read from the code's tables (VPT 0); the more chunks per
             // wave, the fewer waves (the register file holds the frame either way)
+            // checks of degree up to 16, one chunk per wave: z, u of the chunk in registers
+            if constexpr (DMIN == 2 && DMAX == kMaxD) {
+                if (cfg.cpt_tmpl == 1) LPD_GO(1, 0, true, true, 1, false);
+            }
             if constexpr (DMIN == 6 && DMAX == 8) {
                 if (cfg.cpt_tmpl == 1) LPD_GO(1, 0, true, true, 1, false);
                 if (cfg.cpt_tmpl == 2) LPD_GO(2, 0, true, true, 1, false);

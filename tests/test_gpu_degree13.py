@@ -1,9 +1,10 @@
 """Check degree 13: the (3,13) code class of Sec. 5 ([1057,813], stand-in code).
 
-Checks above degree 8 run in the persistent-global and streamed forms, with the
-projection of Algorithm 2 on 9..16 coordinates.  The decoder's state after a fixed
-number of iterations matches the oracle, the two forms give bitwise the same
-decodes, and the forms that do not take such codes refuse them.
+Checks above degree 8 run in the persistent-global and streamed forms, and in the
+resident form when the code needs one chunk per wave, with the projection of
+Algorithm 2 on 9..16 coordinates.  The decoder's state after a fixed number of
+iterations matches the oracle, the forms give bitwise the same decodes, and the
+forms that do not take such codes refuse them.
 """
 import numpy as np
 import pytest
@@ -36,7 +37,8 @@ def host(t):
     return t.cpu().numpy()
 
 
-FORMS = {"persistent_global": 3, "streamed": 2}
+FORMS = {"resident": 1, "persistent_global": 3, "streamed": 2}
+LARGE_FORMS = {"persistent_global": 3, "streamed": 2}
 
 
 def _llr(H, frames, snr, tag):
@@ -65,14 +67,15 @@ def test_code313_decodes_match_oracle_and_agree_across_forms():
     code = lp.Code(H)
     li = code.launch_info()
     print(f"(3,13) n=1057 AUTO: {li}", flush=True)
-    assert li["mode"] == lp.MODE_PERSISTENT_GLOBAL
+    assert li["mode"] == lp.MODE_RESIDENT and code.info["resident_capable"]
     outs = {}
     for name, m in FORMS.items():
         x, it, fl = lp.decode(code, dev(llr), mode=m, **W.PAPER_PARAMS)
         outs[name] = (host(x), host(it), host(fl))
-    a, b = outs["persistent_global"], outs["streamed"]
-    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
-    assert np.abs(a[0] - b[0]).max() == 0.0
+    a = outs["resident"]
+    for b in (outs["persistent_global"], outs["streamed"]):
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+        assert np.abs(a[0] - b[0]).max() == 0.0
     ref = oracle.decode(H, llr, **W.PAPER_PARAMS)
     x, it, fl = a
     ambiguous = np.any(np.abs(ref.x - 0.5) < 1e-3, axis=1)
@@ -88,10 +91,13 @@ def test_code313_large_accumulator_exchange():
     H = W.code313(16380)
     llr = _llr(H, 4, 3.0, "313-large")
     code = lp.Code(H)
+    assert not code.info["resident_capable"]  # four chunks per wave
+    with pytest.raises(lp.LpdecError):
+        lp.decode(code, dev(llr), mode=lp.MODE_RESIDENT)
     K = 12
     ref = oracle.decode(H, llr, mu=3.0, rho=1.9, max_iter=K, tol=0.0, state=True)
     outs = []
-    for name, m in FORMS.items():
+    for name, m in LARGE_FORMS.items():
         print(f"(3,13) n=16380 K={K} form={name}: {code.launch_info(mode=m)}", flush=True)
         x, it, fl, z, u = lp.decode_state(code, dev(llr), tol=0.0, max_iter=K, mode=m)
         x, z, u = host(x), host(z), host(u)
@@ -147,13 +153,10 @@ def test_code313_mixed_with_degree6_code():
         assert np.array_equal(x[off[i]:off[i] + lens[i]], xs[k])
 
 
-def test_code313_unsupported_forms_are_refused():
+def test_code313_dual_is_refused():
     H = W.code313(1057)
     code = lp.Code(H)
-    assert not code.info["resident_capable"]
     llr = dev(_llr(H, 4, 3.0, "313-refuse"))
-    with pytest.raises(lp.LpdecError):
-        lp.decode(code, llr, mode=lp.MODE_RESIDENT)
     with pytest.raises(lp.LpdecError) as e:
         lp.decode_dual(code, llr)
     assert "degree" in str(e.value)
