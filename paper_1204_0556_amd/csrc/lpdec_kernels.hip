@@ -369,26 +369,24 @@ __device__ __forceinline__ float x_update(const float *slots, const VarLoc &L, f
 }
 
 // Exact, order-independent per-variable sums for codes whose slot array does not
-// fit in LDS: each replica difference w is converted to signed 32.32 fixed point,
-// floor(w 2^32) (exact for 2^-9 <= |w| < 2^31; smaller magnitudes are rounded
-// toward -infinity to a multiple of 2^-32; w is first clamped to [-2^31, 2^31 - 128],
-// the largest float below 2^31), and accumulated with 64-bit integer LDS atomics.
-// Integer addition is associative, so the sum does not depend on the order the
-// lanes arrive in.  The conversion is branch-free FP32/integer arithmetic: the
+// fit in LDS: each replica difference w (first clamped to [-2^31, 2^31 - 128], the
+// largest float below 2^31) is converted to a signed 32.32 fixed-point value and
+// accumulated with 64-bit integer LDS atomics.  Integer addition is associative, so
+// the sum does not depend on the order the lanes arrive in.  The conversion rounds
+// down to a multiple of 2^-32, strictly so for negative w: with t = trunc(|w| 2^32),
+// the value is t when the sign bit of w is clear and the bitwise complement of t,
+// -t - 1, when it is set (-0.0 included): an error of at most 2^-32 either way.  It is branch-free FP32/integer arithmetic: the
 // magnitude splits exactly into its integer part and its fraction (the difference
-// of a float and its floor is exact), the fraction scaled by 2^32 is an exact float
-// whose integer part is the low word, and a negative value is the two's complement
-// of the magnitude rounded up (bits below 2^-32 make the floor one step lower).
+// of a float and its floor is exact), and the fraction scaled by 2^32 is an exact
+// float whose integer part is the low word.
 __device__ __forceinline__ unsigned long long to_fixed(float w) {
     const float c = __builtin_amdgcn_fmed3f(w, -2147483648.0f, 2147483520.0f);
     const float a = fabsf(c);
     const float ah = floorf(a);
     const float r = (a - ah) * 4294967296.0f;  // in [0, 2^32)
     const unsigned hi = (unsigned)ah, lo = (unsigned)r;
-    const bool cut = r != truncf(r);
     const unsigned m = (unsigned)(__float_as_int(c) >> 31);  // all ones when negative
-    const unsigned long long v = ((unsigned long long)(hi ^ m) << 32) | (lo ^ m);
-    return v + ((m != 0u && !cut) ? 1ull : 0ull);
+    return ((unsigned long long)(hi ^ m) << 32) | (lo ^ m);
 }
 // The sum back to FP32: a correctly rounded conversion of the signed 64-bit value
 // (integer normalisation, no FP64), then an exact scale by 2^-32.
