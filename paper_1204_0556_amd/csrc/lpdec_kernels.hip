@@ -469,12 +469,24 @@ __device__ __forceinline__ void st_state(void *p, size_t i, float a) {
     if constexpr (HALF) as_global_rw(static_cast<unsigned short *>(p))[i] = __half_as_ushort(__float2half_rn(a));
     else as_global_rw(static_cast<float *>(p))[i] = a;
 }
-// Two FP16 state values in one register (a in the low half), rounded as st_state rounds.
+// Two FP16 state values in one register (a in the low half), rounded as st_state rounds
+// (to nearest even): one packed conversion instead of two conversions and an OR.
+typedef float lpd_f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 lpd_f16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ unsigned pack_h2(float a, float b) {
-    return (unsigned)__half_as_ushort(__float2half_rn(a)) | ((unsigned)__half_as_ushort(__float2half_rn(b)) << 16);
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((lpd_f32x2){a, b}, lpd_f16x2));
 }
 __device__ __forceinline__ float lo_h2f(unsigned v) { return __half2float(__ushort_as_half((unsigned short)(v & 0xffffu))); }
 __device__ __forceinline__ float hi_h2f(unsigned v) { return __half2float(__ushort_as_half((unsigned short)(v >> 16))); }
+// lo - hi of a packed pair in one mixed-precision FMA: lo * 1 + (-hi) with both
+// halves read as FP16 and one FP32 rounding, the value lo_h2f(v) - hi_h2f(v) has
+// (the compiler rewrites an FMA by 1 into an add of two widened halves, three
+// instructions, so it is written out).
+__device__ __forceinline__ float packed_diff(unsigned v) {
+    float w;
+    asm("v_fma_mix_f32 %0, %1, 1.0, -%1 op_sel:[0,0,1] op_sel_hi:[1,0,1]" : "=v"(w) : "v"(v));
+    return w;
+}
 
 // ---------------------------------------------------------------------------
 // The decoder kernel.
@@ -1745,7 +1757,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                     if (hval[k]) {
 #pragma unroll
                         for (int e = 0; e < D; ++e) {
-                            const float w = PK ? lo_h2f(hr[k][e]) - hi_h2f(hr[k][e]) : zr[PK ? 0 : k][e] - ur[PK ? 0 : k][e];
+                            const float w = PK ? packed_diff(hr[k][e]) : zr[PK ? 0 : k][e] - ur[PK ? 0 : k][e];
                             atomicAdd(acc_entry(acc, mcur[e]), to_fixed(w));
                         }
                     }
