@@ -398,6 +398,21 @@ __device__ __forceinline__ float from_fixed(unsigned long long a) {
 __device__ __forceinline__ unsigned long long *acc_entry(unsigned long long *acc, uint32_t off) {
     return reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(acc) + off);
 }
+// LDS byte address a as a pointer.  For a kernel without static LDS the dynamic
+// array starts at address 0, so an entry's byte offset is its address: the access
+// needs no add of the array's address (a link-time symbol that the compiler does
+// not fold into the instruction's offset field).
+template <typename T>
+__device__ __forceinline__ T *lds_at(uint32_t a) {
+    return (T *)(__attribute__((address_space(3))) T *)(size_t)a;
+}
+// k_decode_acc's residual slots, frame index and certificate votes follow its 8 n
+// bytes of accumulators (from the next 16-byte boundary); kAccTailBytes of dynamic LDS
+// hold them, the 8 bytes the alignment may skip included.
+__host__ __device__ constexpr uint32_t acc_tail_offset(int n) { return (8u * (uint32_t)n + 15u) & ~15u; }
+constexpr size_t kAccFrameOffset = sizeof(float) * 2 * 2 * kMaxWaves;  // after s_red
+constexpr size_t kAccVoteOffset = kAccFrameOffset + 16;                // two votes per wave
+constexpr size_t kAccTailBytes = kAccVoteOffset + sizeof(int) * 2 * kMaxWaves + 16;
 
 // Accumulator exchange, variable phase: x_i of variables tid, tid + NT, ... from
 // the variable's accumulator entry (less the previous x its high word still holds,
@@ -1568,9 +1583,9 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
     static_assert(VW == 1 || (VW == 2 && PERSIST && !WALK), "two plan waves per wave: all chunks held");
     constexpr int NH = VW * KR;                // held chunks per hardware wave
     constexpr int NHA = NH > 0 ? NH : 1;
+    // no static LDS (the launcher checks): the dynamic array starts at address 0, and
+    // the accumulator atomics and x reads address LDS by the entries' byte offsets
     extern __shared__ __attribute__((aligned(16))) float lds[];
-    __shared__ float s_red[2][2][kMaxWaves];
-    __shared__ int s_frame;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1579,7 +1594,11 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
     const DevCode &C = codes[0];
     const int W = C.waves, cpt = C.cpt;  // the plan's waves (NW = W when VW = 1)
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(lds);
-    const float *xs = lds + 1;  // x sits in each accumulator's high word (stride 2)
+    const float *xs = lds_at<const float>(4);  // x sits in each accumulator's high word (stride 2)
+    char *tail = reinterpret_cast<char *>(lds) + acc_tail_offset(C.n);
+    float(*s_red)[2][kMaxWaves] = reinterpret_cast<float(*)[2][kMaxWaves]>(tail);
+    int &s_frame = *reinterpret_cast<int *>(tail + kAccFrameOffset);
+    int *s_vote = reinterpret_cast<int *>(tail + kAccVoteOffset);
     unsigned *xprev = PERSIST ? sa.gxprev + (size_t)blockIdx.x * sa.gmu_stride : nullptr;
     const float thr = ip.tol2 * (float)C.E;
 
@@ -1758,7 +1777,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
 #pragma unroll
                         for (int e = 0; e < D; ++e) {
                             const float w = PK ? packed_diff(hr[k][e]) : zr[PK ? 0 : k][e] - ur[PK ? 0 : k][e];
-                            atomicAdd(acc_entry(acc, mcur[e]), to_fixed(w));
+                            atomicAdd(lds_at<unsigned long long>(mcur[e]), to_fixed(w));
                         }
                     }
 #pragma unroll
@@ -1779,7 +1798,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
                 if (nxt.has) walk_load(nxt, zn, un, mn);
                 if (lane < cur.cnt) {
 #pragma unroll
-                    for (int e = 0; e < D; ++e) atomicAdd(acc_entry(acc, mc[e]), to_fixed(zc[e] - uc[e]));
+                    for (int e = 0; e < D; ++e) atomicAdd(lds_at<unsigned long long>(mc[e]), to_fixed(zc[e] - uc[e]));
                 }
 #pragma unroll
                 for (int e = 0; e < D; ++e) {
@@ -1945,9 +1964,19 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
         }
         // frac > 1e-3 exactly: 1e-3f is the least float above 1e-3
         const bool nonint = frac >= 1e-3f;
-        const int any_odd = __syncthreads_or(odd);
-        const int any_nonint = __syncthreads_or(nonint);
+        // workgroup votes through the LDS tail (a library vote would bring static LDS)
+        const bool wodd = __ballot(odd) != 0ull, wnonint = __ballot(nonint) != 0ull;
+        if (lane == 0) {
+            s_vote[wave] = wodd;
+            s_vote[kMaxWaves + wave] = wnonint;
+        }
+        __syncthreads();
         if (tid == 0) {
+            int any_odd = 0, any_nonint = 0;
+            for (int w = 0; w < NW; ++w) {
+                any_odd |= s_vote[w];
+                any_nonint |= s_vote[kMaxWaves + w];
+            }
             uint8_t fl = conv ? 0x01 : 0x00;
             if (!any_nonint) fl |= 0x02;
             if (!any_odd) fl |= 0x04;
@@ -2171,15 +2200,25 @@ static hipError_t go_pair(const LaunchConfig &cfg, const DevCode *codes, const F
     return hipGetLastError();
 }
 
+static int static_lds_bytes(const void *kern) {
+    hipFuncAttributes fa{};
+    return hipFuncGetAttributes(&fa, kern) == hipSuccess ? (int)fa.sharedSizeBytes : -1;
+}
+
 // large check-regular codes with the accumulator exchange (see k_decode_acc)
 template <int D, int KR, bool HALF, bool PERSIST, int VW = 1>
 static hipError_t go_acc1(const LaunchConfig &cfg, const DevCode *codes, const FrameBatch &fb, const IterParams &ip,
                           const StateIO &sio, const StreamArgs &sa, hipStream_t stream, KernelQuery *q) {
     if (cfg.threads > kMaxThreads / VW) return hipErrorInvalidConfiguration;
     auto kern = k_decode_acc<D, KR, HALF, PERSIST, VW>;
-    if (cfg.lds_bytes > 64 * 1024) {
+    // the kernel addresses LDS absolutely: its dynamic array must start at address 0
+    static const int static_lds = static_lds_bytes(reinterpret_cast<const void *>(kern));
+    if (static_lds != 0) return hipErrorInvalidConfiguration;
+    // the 8 n bytes of accumulators, then the residual slots and the frame index
+    const size_t lds = cfg.lds_bytes + kAccTailBytes;
+    if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg.lds_bytes);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     if (q) {
@@ -2187,10 +2226,10 @@ static hipError_t go_acc1(const LaunchConfig &cfg, const DevCode *codes, const F
         hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kern));
         if (e != hipSuccess) return e;
         q->vgprs = fa.numRegs;
-        q->static_lds = (int)fa.sharedSizeBytes;
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&q->occupancy, kern, cfg.threads, cfg.lds_bytes);
+        q->static_lds = (int)kAccTailBytes;  // the tail plays the part of static LDS
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&q->occupancy, kern, cfg.threads, lds);
     }
-    hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(cfg.threads), cfg.lds_bytes, stream, codes, fb, ip, sio, sa,
+    hipLaunchKernelGGL(kern, dim3(cfg.grid), dim3(cfg.threads), lds, stream, codes, fb, ip, sio, sa,
                        cfg.state_stride);
     return hipGetLastError();
 }
