@@ -3,8 +3,10 @@
 * gamma = 0 (a zero-cost LP: the iteration stays at the all-zero point and certifies it);
 * saturated channels (|gamma| of 1e4) where every x clips at once;
 * LLRs that are exactly zero on some bits (the x-update has no channel pull there);
-* single-check codes of every degree 2..8 (the LP optimum is Algorithm 3's vertex);
-* a code whose checks have degrees 2..8 together (the general-degree kernels).
+* single-check codes of every degree 2..8 and of degrees 9, 12, 13 and 16 (the LP
+  optimum is Algorithm 3's vertex);
+* a code whose checks have degrees 2..8 together (the general-degree kernels), and one
+  whose checks have degrees 2..16 (the build for checks above degree 8).
 """
 import numpy as np
 import pytest
@@ -73,13 +75,14 @@ def test_saturated_and_exactly_zero_llrs():
     assert np.all(np.all((host(x) >= 0.5) == (ref.x >= 0.5), axis=1) | ambiguous)
 
 
-@pytest.mark.parametrize("d", [2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("d", [2, 3, 4, 5, 6, 7, 8, 9, 12, 13, 16])
 def test_single_check_codes(d):
     H = W.single_check(d)
     rng = np.random.default_rng([d, 5])
     llr = rng.normal(0.5, 2.0, (64, d)).astype(np.float32)
     print(f"single check d={d}", flush=True)
-    modes = FORMS if d == 6 else (lp.MODE_PERSISTENT_GLOBAL, lp.MODE_STREAMED)
+    # resident builds: degree 6, and one chunk per wave above degree 8
+    modes = FORMS if (d == 6 or d > 8) else (lp.MODE_PERSISTENT_GLOBAL, lp.MODE_STREAMED)
     _check_fixed_k(H, llr, 25, modes)
     x, it, fl = lp.decode(lp.Code(H), dev(llr), max_iter=5000, tol=1e-7)
     ref = oracle.decode(H, llr, max_iter=5000, tol=1e-7)
@@ -104,3 +107,29 @@ def test_check_degrees_two_to_eight_in_one_code():
     llr = W.awgn_batch(H, 16, 2.0, tag="deg2to8")
     print(f"degrees 2..8 code m={m} n={n} nnz={H.nnz}", flush=True)
     _check_fixed_k(H, llr, 40, (lp.MODE_PERSISTENT_GLOBAL, lp.MODE_STREAMED))
+
+
+def test_check_degrees_two_to_sixteen_in_one_code():
+    rng = np.random.default_rng(23)
+    m, n = 45, 120
+    while True:  # random H with row degrees spread over 2..16 and no empty column
+        degs = rng.integers(2, 17, size=m)
+        rows = np.repeat(np.arange(m), degs)
+        cols = np.concatenate([rng.choice(n, d, replace=False) for d in degs])
+        vdeg = np.bincount(cols, minlength=n)
+        if vdeg.min() >= 1 and np.unique(vdeg).size <= 8 and set(degs) == set(range(2, 17)):
+            break
+    order = np.lexsort((cols, rows))
+    rows, cols = rows[order], cols[order]
+    row_ptr = np.zeros(m + 1, np.int32)
+    np.cumsum(np.bincount(rows, minlength=m), out=row_ptr[1:])
+    H = W.ParityCheckMatrix(m, n, row_ptr, cols.astype(np.int32), "degrees 2..16")
+    llr = W.awgn_batch(H, 16, 2.0, tag="deg2to16")
+    code = lp.Code(H)
+    print(f"degrees 2..16 code m={m} n={n} nnz={H.nnz}: {code.launch_info()}", flush=True)
+    assert code.info["resident_capable"]  # one chunk per degree, one wave each
+    _check_fixed_k(H, llr, 40, FORMS)
+    outs = [tuple(host(t) for t in lp.decode(code, dev(llr), mode=md, max_iter=300)) for md in FORMS]
+    for o in outs[1:]:
+        assert np.array_equal(o[1], outs[0][1]) and np.array_equal(o[2], outs[0][2])
+        assert np.abs(o[0] - outs[0][0]).max() == 0.0
