@@ -46,11 +46,15 @@ def _same(ref, got, what):
 # in the resident form (the first batch is large enough for two frames per
 # workgroup), an irregular code with degree 6..8 checks (resident, gamma/mu staged
 # in the array), and a code too large for registers (persistent-global: state,
-# previous x and gamma/mu per workgroup in the array, grid cut to fit)
+# previous x and gamma/mu per workgroup in the array, grid cut to fit); and the
+# (3,13) code class: one chunk per wave (resident) and n = 16380 (persistent-global,
+# fixed-point accumulators, checks of degree 13)
 CASES = {
     "n2640_resident": (lambda: W.gallager36(2640), 600, 40, 300, lp.MODE_RESIDENT),
     "n8064_irregular": (lambda: W.irregular_half(8064), 300, 20, 200, lp.MODE_RESIDENT),
     "n16384_persistent_global": (lambda: W.gallager36(16384), 300, 16, 60, lp.MODE_PERSISTENT_GLOBAL),
+    "n1057_degree13_resident": (lambda: W.code313(1057), 600, 40, 300, lp.MODE_RESIDENT),
+    "n16380_degree13_persistent_global": (lambda: W.code313(16380), 200, 12, 40, lp.MODE_PERSISTENT_GLOBAL),
 }
 
 
