@@ -882,11 +882,15 @@ lpdec_status lpdec_decode_core(const lpdec_code *const *codes, int ncodes, int n
         HIP_TRY(ws.u.ensure(esz * per * nframes));
         HIP_TRY(ws.st.ensure(sizeof(StreamFrame) * nframes));
         HIP_TRY(ws.active.ensure(sizeof(int) * 2));
+        HIP_TRY(ws.alist.ensure(sizeof(int) * 2 * (size_t)nframes));
+        HIP_TRY(ws.alist_cnt.ensure(sizeof(int) * 3));
         if (!ws.host_active) HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&ws.host_active), 2 * sizeof(int)));
         sa.z = ws.z.p;
         sa.u = ws.u.p;
         sa.st = static_cast<StreamFrame *>(ws.st.p);
         sa.active_count = static_cast<int *>(ws.active.p);
+        sa.alist = static_cast<int *>(ws.alist.p);
+        sa.alist_cnt = static_cast<int *>(ws.alist_cnt.p);
         if (s.permuted) {
             HIP_TRY(ws.gmu.ensure(sizeof(float) * (size_t)nframes * s.nmax));
             sa.gmu = static_cast<float *>(ws.gmu.p);

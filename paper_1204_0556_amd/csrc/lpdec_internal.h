@@ -108,6 +108,12 @@ struct StreamArgs {
     StreamFrame *st;        // [frames]
     int *active_count;      // [2] frames still running after a launch: launch k counts into
                             // entry k & 1 and clears the other one for launch k + 1
+    int *alist;             // [2][frames] the frames still running after a launch, in the
+                            // order they finished it: launch k appends to half k & 1 and
+                            // works through half (k + 1) & 1, dealing its entries to the
+                            // workgroups in turn (k_stream_init lists every frame there)
+    int *alist_cnt;         // [3] entries of each list: launch k appends at entry k % 3,
+                            // reads entry (k + 2) % 3 and clears entry (k + 1) % 3
     float *gslots;          // [workgroups][slot_stride] slot scratch when slots live in global memory
     float *gmu;             // gamma/mu in internal variable order: [workgroups or frames][gmu_stride]
     unsigned *gxprev;       // accumulator mode, persistent form: previous x bits [workgroups][gmu_stride]
@@ -125,7 +131,8 @@ struct LaunchConfig {
     int cpt_tmpl;      // register-held chunks per wave: 0 (re-read), 2 or 4
     int vpt_tmpl;      // register-held variables per thread (resident form): 4 or 8
     int dclass;        // 0: degrees exactly 6; 1: degrees 2..8; 2: degrees 6..8 (resident form);
-                       // 3: degrees 2..16 (persistent-global and streamed forms)
+                       // 3: degrees 2..16 (resident form with one chunk per wave, the
+                       // persistent-global and streamed forms)
     int dv;            // every variable has this degree (0: mixed), resident form
     int slot_mode;     // 0 global float slots, 1 LDS float slots, 2 LDS fixed-point accumulators
     bool half;         // fp16 state storage (streamed only)

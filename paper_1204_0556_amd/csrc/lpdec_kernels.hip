@@ -590,26 +590,48 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
     // Streamed form: this workgroup owns frames blockIdx.x + k*G (G = gridDim.x).
     // Their done-flags are read 64 at a time (one per lane) and the unfinished
     // ones taken from a ballot mask, identical in every wave.
-    int sbase = (int)blockIdx.x - kWave * (int)gridDim.x;
-    unsigned long long smask = 0ull;
+    const int launch = PERSIST ? 0 : streamed_launch(ip, sa);
+    // Streamed form: the frames still running after the previous launch, listed in
+    // the order they finished it, are dealt to the workgroups in turn (entry
+    // blockIdx.x + k G, G = gridDim.x), so every workgroup gets the same number of
+    // frames to within one however few remain.  Each frame that stays unfinished
+    // appends itself to this launch's list.
+    // The list entries are read 64 at a time (one per lane, with their done flags)
+    // and the unfinished frames taken from a ballot mask, identical in every wave.
+    int lcnt = 0;
+    const int *lprev = nullptr;
+    if constexpr (!PERSIST) {
+        lcnt = min(uniform_i32(sa.alist_cnt[(launch + 2) % 3]), fb.nframes);
+        lprev = sa.alist + (size_t)((launch + 1) & 1) * fb.nframes;
+        if (blockIdx.x == 0 && tid == 0) {
+            sa.active_count[(launch + 1) & 1] = 0;  // next launch's counter
+            sa.alist_cnt[(launch + 1) % 3] = 0;     // next launch's list
+        }
+    }
+    int lbase = (int)blockIdx.x - kWave * (int)gridDim.x;
+    int lframe = 0;  // this lane's frame of the current group of entries
+    unsigned long long lmask = 0ull;
     auto next_active = [&]() -> int {
         for (;;) {
-            if (smask) {
-                const int j = __builtin_ctzll(smask);
-                smask &= smask - 1ull;
-                return sbase + j * (int)gridDim.x;
+            if (lmask) {
+                const int j = __builtin_ctzll(lmask);
+                lmask &= lmask - 1ull;
+                return __builtin_amdgcn_readlane(lframe, j);
             }
-            sbase += kWave * (int)gridDim.x;
-            if (sbase >= fb.nframes) return fb.nframes;
-            const int fj = sbase + lane * (int)gridDim.x;
-            const bool act = fj < fb.nframes && !sa.st[fj].done;
-            smask = __ballot(act);
+            lbase += kWave * (int)gridDim.x;
+            if (lbase >= lcnt) return fb.nframes;
+            const int lj = lbase + lane * (int)gridDim.x;
+            const int g = lj < lcnt ? lprev[lj] : -1;
+            lframe = g;
+            lmask = __ballot(g >= 0 && g < fb.nframes && !sa.st[g].done);
         }
     };
-    const int launch = PERSIST ? 0 : streamed_launch(ip, sa);
-    if constexpr (!PERSIST) {
-        if (blockIdx.x == 0 && tid == 0) sa.active_count[(launch + 1) & 1] = 0;  // next launch's counter
-    }
+    // a frame that stays unfinished: count it and list it for the next launch
+    auto list_unfinished = [&](int g) {
+        atomicAdd(sa.active_count + (launch & 1), 1);
+        const int pos = atomicAdd(sa.alist_cnt + launch % 3, 1);
+        if (pos < fb.nframes) sa.alist[(size_t)(launch & 1) * fb.nframes + pos] = g;
+    };
     // STG: start the direct-to-LDS copy of frame g's z, u (16 bytes per lane) and
     // gamma/mu (4 bytes per lane); each wave copies every NW-th 1 KB block
     auto stage_issue = [&](const DevCode &Cg, int g) {
@@ -1129,7 +1151,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
             if (tid == 0) {
                 sa.st[f].iter = it;
                 if (fin) sa.st[f].done = 1;
-                else atomicAdd(sa.active_count + (launch & 1), 1);
+                else list_unfinished(f);
             }
             if (!fin) {
                 pbar();  // LDS reuse by the next frame of this workgroup
@@ -1618,26 +1640,48 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
     float zr[PK ? 1 : NHA][D], ur[PK ? 1 : NHA][D];
     unsigned hr[PK ? NHA : 1][D];  // PK: z | u << 16 (FP16 bits) of held edge e of chunk h
 
-    int sbase = (int)blockIdx.x - kWave * (int)gridDim.x;
-    unsigned long long smask = 0ull;
+    const int launch = PERSIST ? 0 : streamed_launch(ip, sa);
+    // Streamed form: the frames still running after the previous launch, listed in
+    // the order they finished it, are dealt to the workgroups in turn (entry
+    // blockIdx.x + k G, G = gridDim.x), so every workgroup gets the same number of
+    // frames to within one however few remain.  Each frame that stays unfinished
+    // appends itself to this launch's list.
+    // The list entries are read 64 at a time (one per lane, with their done flags)
+    // and the unfinished frames taken from a ballot mask, identical in every wave.
+    int lcnt = 0;
+    const int *lprev = nullptr;
+    if constexpr (!PERSIST) {
+        lcnt = min(uniform_i32(sa.alist_cnt[(launch + 2) % 3]), fb.nframes);
+        lprev = sa.alist + (size_t)((launch + 1) & 1) * fb.nframes;
+        if (blockIdx.x == 0 && tid == 0) {
+            sa.active_count[(launch + 1) & 1] = 0;  // next launch's counter
+            sa.alist_cnt[(launch + 1) % 3] = 0;     // next launch's list
+        }
+    }
+    int lbase = (int)blockIdx.x - kWave * (int)gridDim.x;
+    int lframe = 0;  // this lane's frame of the current group of entries
+    unsigned long long lmask = 0ull;
     auto next_active = [&]() -> int {
         for (;;) {
-            if (smask) {
-                const int j = __builtin_ctzll(smask);
-                smask &= smask - 1ull;
-                return sbase + j * (int)gridDim.x;
+            if (lmask) {
+                const int j = __builtin_ctzll(lmask);
+                lmask &= lmask - 1ull;
+                return __builtin_amdgcn_readlane(lframe, j);
             }
-            sbase += kWave * (int)gridDim.x;
-            if (sbase >= fb.nframes) return fb.nframes;
-            const int fj = sbase + lane * (int)gridDim.x;
-            const bool act = fj < fb.nframes && !sa.st[fj].done;
-            smask = __ballot(act);
+            lbase += kWave * (int)gridDim.x;
+            if (lbase >= lcnt) return fb.nframes;
+            const int lj = lbase + lane * (int)gridDim.x;
+            const int g = lj < lcnt ? lprev[lj] : -1;
+            lframe = g;
+            lmask = __ballot(g >= 0 && g < fb.nframes && !sa.st[g].done);
         }
     };
-    const int launch = PERSIST ? 0 : streamed_launch(ip, sa);
-    if constexpr (!PERSIST) {
-        if (blockIdx.x == 0 && tid == 0) sa.active_count[(launch + 1) & 1] = 0;  // next launch's counter
-    }
+    // a frame that stays unfinished: count it and list it for the next launch
+    auto list_unfinished = [&](int g) {
+        atomicAdd(sa.active_count + (launch & 1), 1);
+        const int pos = atomicAdd(sa.alist_cnt + launch % 3, 1);
+        if (pos < fb.nframes) sa.alist[(size_t)(launch & 1) * fb.nframes + pos] = g;
+    };
     for (;;) {
         int f;
         if constexpr (PERSIST) {
@@ -1937,7 +1981,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
             if (tid == 0) {
                 sa.st[f].iter = it;
                 if (fin) sa.st[f].done = 1;
-                else atomicAdd(sa.active_count + (launch & 1), 1);
+                else list_unfinished(f);
             }
             if (!fin) {
                 wg_barrier<true>();  // LDS reuse by the next frame of this workgroup
@@ -2028,6 +2072,13 @@ k_stream_init(const DevCode *__restrict__ codes, FrameBatch fb, StateIO sio, Str
     const int f = blockIdx.x;
     if (f >= fb.nframes) return;
     if (f == 0 && threadIdx.x < 2) sa.active_count[threadIdx.x] = 0;
+    // every frame is on the list launch 0 works through (as if launch -1 had made it);
+    // launch 0 appends at entry 0
+    if (threadIdx.x == 0) sa.alist[(size_t)fb.nframes + f] = f;
+    if (f == 0 && threadIdx.x == 0) {
+        sa.alist_cnt[2] = fb.nframes;
+        sa.alist_cnt[0] = 0;
+    }
     const int ci = fb.code_of_frame ? uniform_i32(fb.code_of_frame[f]) : 0;
     const DevCode &C = codes[ci];
     const int64_t loff = fb.llr_off ? uniform_i64(fb.llr_off[f]) : (int64_t)f * C.n;

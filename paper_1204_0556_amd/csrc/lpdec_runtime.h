@@ -45,6 +45,7 @@ struct Workspace {
     DevBuf codes;      // DevCode array (multi-code launches)
     DevBuf frame_meta; // code_of_frame / offsets
     DevBuf z, u, st, active, gslots, gstate, gmu, gxprev;
+    DevBuf alist, alist_cnt;  // streamed form: the unfinished frames of the last launch
     int *host_active = nullptr; // pinned
     char *host_meta = nullptr;  // pinned staging for per-call metadata
     size_t host_meta_bytes = 0;
@@ -57,7 +58,7 @@ struct Workspace {
     ~Workspace() {
         queue.release(); codes.release(); frame_meta.release();
         z.release(); u.release(); st.release(); active.release(); gslots.release(); gstate.release();
-        gmu.release(); gxprev.release(); launch_dev.release();
+        gmu.release(); gxprev.release(); launch_dev.release(); alist.release(); alist_cnt.release();
         if (graph) (void)hipGraphExecDestroy(graph);
         if (capture) (void)hipStreamDestroy(capture);
         if (host_active) (void)hipHostFree(host_active);
