@@ -892,6 +892,11 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         };
 
         auto phase_b = [&]() {
+            // the thread index through an empty asm: the per-thread address arithmetic of
+            // this phase is then formed here each time instead of being hoisted to the
+            // kernel's start, where its values stayed live and spilled to scratch
+            int tb = tid;
+            asm volatile("" : "+v"(tb));
             if constexpr (VPT > 0 && DV > 0) {
                 constexpr float inv = 1.0f / (float)DV;
 #pragma unroll
@@ -923,7 +928,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                 if constexpr (STG) {  // gamma/mu taken from the staging area in phase A
 #pragma unroll
                     for (int t = 0; t < GQ; ++t) {
-                        const int i = tid + t * NT;
+                        const int i = tb + t * NT;
                         if (i < C.n) {
                             const int b = C.dv * i;
                             float acc = 0.0f;
@@ -932,7 +937,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                         }
                     }
                 } else if (C.dv > 0) {  // kernel-uniform degree: four variables per pass, loads first
-                    for (int i0 = tid; i0 < C.n; i0 += 4 * NT) {
+                    for (int i0 = tb; i0 < C.n; i0 += 4 * NT) {
                         float g[4];
 #pragma unroll
                         for (int t = 0; t < 4; ++t) {
@@ -963,7 +968,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
                         auto sums = [&](auto dc) {
                             constexpr int DVC = decltype(dc)::value;
                             constexpr int VC = 2;  // variables per pass
-                            for (int i0 = b + tid; i0 < end; i0 += VC * NT) {
+                            for (int i0 = b + tb; i0 < end; i0 += VC * NT) {
                                 float g[VC];
 #pragma unroll
                                 for (int t = 0; t < VC; ++t) {
