@@ -464,7 +464,9 @@ int acc_held_chunks(const Shape &s, bool persistent, int variant, int *nvariants
     // defaults [persistent][degree 8] from the precision batches (8192 frames at
     // 2.5 dB): streamed (3,6) n = 16384 49.8 / 51.2 / 53.8 ms for KR = -1 / 0 / 2,
     // (4,8) 164.5 / 160.2 / 187.5 ms; persistent-global (3,6) 38.0 / 37.5 / 35.5 ms
-    // for KR = -1 / 0 / 1, (4,8) 125.4 / 113.0 / 105.3 ms
+    // for KR = -1 / 0 / 1, (4,8) 125.4 / 113.0 / 105.3 ms.  Since the streamed form's
+    // per-launch frame lists, streamed (4,8) FP32 runs 141.3 / 140.2 / 136.3 ms for KR =
+    // -1 / 0 / 2 and takes KR = 2, while FP16 storage keeps KR = 0 (114.2 / 110.7 / 144.0)
     static const int kDefault[2][2] = {{0, 1}, {2, 2}};
     const int *t = nullptr;
     int nt = 0;
@@ -483,7 +485,10 @@ int acc_held_chunks(const Shape &s, bool persistent, int variant, int *nvariants
     if (!t || s.ncodes != 1) return -1;
     // FP32 persistent-global degree 6: every chunk held at two plan waves per wave where
     // the code allows it ((3,6) n = 16384: 29.4 ms against 35.7 ms for one held chunk)
-    const int def = ph ? 0 : (persistent && s.dreg == 6 && nt == 4 ? 3 : kDefault[persistent][s.dreg == 8]);
+    const int def = ph ? 0
+                       : (persistent && s.dreg == 6 && nt == 4
+                              ? 3
+                              : (!persistent && !half && s.dreg == 8 ? 2 : kDefault[persistent][s.dreg == 8]));
     const int v = variant < 0 ? def : std::min(variant, nt - 1);
     return t[v];
 }
@@ -545,7 +550,7 @@ void streamed_config(const Shape &s, bool half, LaunchConfig *cfg, int variant =
     cfg->lds_E = s.Emax;
     cfg->slot_stride = s.Emax;
     cfg->state_stride = 0;
-    cfg->acc_kr = cfg->slot_mode == 2 ? acc_held_chunks(s, false, variant) : -1;
+    cfg->acc_kr = cfg->slot_mode == 2 ? acc_held_chunks(s, false, variant, nullptr, half) : -1;
     cfg->acc = cfg->acc_kr >= 0;
     cfg->acc_d = cfg->acc ? s.dreg : 0;
 }
