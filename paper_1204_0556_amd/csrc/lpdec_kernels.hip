@@ -238,23 +238,23 @@ __device__ __forceinline__ int streamed_launch(const IterParams &ip, const Strea
 
 // Sum over the 64 lanes of a wavefront, returned in every lane.  DPP steps sum
 // each row of 16 lanes (quad_perm xor 1, xor 2, half-row mirror, row mirror; every
-// lane of a row ends with bitwise the same value since float addition commutes),
-// then the four row sums are read from lanes 0/16/32/48 and added in a fixed order.
-// No LDS traffic, and the same order in every wave and every kernel form.
-template <int CTRL>
+// lane of a row ends with bitwise the same value since float addition commutes).
+// Two row broadcasts then combine the row sums R0..R3: lane 15 of rows 0 and 2 into
+// rows 1 and 3 (R1 + R0, R3 + R2), lane 31 into row 3 ((R3 + R2) + (R1 + R0)), read
+// from lane 63 -- by commutativity bitwise (R0 + R1) + (R2 + R3).  No LDS traffic,
+// and the same order in every wave and every kernel form.
+template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ float dpp_shift(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xF, ROWS == 0xF));
 }
 __device__ __forceinline__ float wave_sum(float x) {
-    x += dpp_shift<0xB1>(x);   // quad_perm [1,0,3,2]
-    x += dpp_shift<0x4E>(x);   // quad_perm [2,3,0,1]
-    x += dpp_shift<0x141>(x);  // row_half_mirror
-    x += dpp_shift<0x140>(x);  // row_mirror
-    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
-    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
-    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
-    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
-    return (r0 + r1) + (r2 + r3);
+    x += dpp_shift<0xB1>(x);         // quad_perm [1,0,3,2]
+    x += dpp_shift<0x4E>(x);         // quad_perm [2,3,0,1]
+    x += dpp_shift<0x141>(x);        // row_half_mirror
+    x += dpp_shift<0x140>(x);        // row_mirror
+    x += dpp_shift<0x142, 0xA>(x);   // row_bcast:15 into rows 1 and 3 (rows 0, 2 add 0)
+    x += dpp_shift<0x143, 0x8>(x);   // row_bcast:31 into row 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
 // Workgroup barrier.  With LDS_ONLY the release/acquire fences cover LDS only, so
