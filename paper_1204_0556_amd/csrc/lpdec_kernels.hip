@@ -256,6 +256,16 @@ __device__ __forceinline__ float wave_sum(float x) {
     x += dpp_shift<0x143, 0x8>(x);   // row_bcast:31 into row 3
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
+// wave_sum of values that are +0 outside lanes 0..15 and never -0 (the per-wave
+// residual partials of the stopping test, one lane per wave of the workgroup): the
+// other rows sum to +0, and R0 + (+0) = R0, so the row steps alone give the same bits.
+__device__ __forceinline__ float row0_sum(float x) {
+    x += dpp_shift<0xB1>(x);
+    x += dpp_shift<0x4E>(x);
+    x += dpp_shift<0x141>(x);
+    x += dpp_shift<0x140>(x);
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
+}
 
 // Workgroup barrier.  With LDS_ONLY the release/acquire fences cover LDS only, so
 // global stores still in flight (the previous phase's z, u) do not have to land
@@ -1089,7 +1099,7 @@ k_decode(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, StateI
         auto converged = [&](int buf) -> bool {  // identical result in every wave
             const float a = lane < NW ? s_red[buf][0][lane] : 0.0f;
             const float b = lane < NW ? s_red[buf][1][lane] : 0.0f;
-            return wave_sum(a) < thr && wave_sum(b) < thr;
+            return row0_sum(a) < thr && row0_sum(b) < thr;
         };
 
         int iters;
@@ -1349,7 +1359,7 @@ k_decode_pair(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, S
     auto converged = [&](int s) -> bool {  // identical result in every wave
         const float a = lw ? s_red[s][0][lane] : 0.0f;
         const float b = lw ? s_red[s][1][lane] : 0.0f;
-        return __builtin_amdgcn_readfirstlane(wave_sum(a) < thr && wave_sum(b) < thr);
+        return __builtin_amdgcn_readfirstlane(row0_sum(a) < thr && row0_sum(b) < thr);
     };
 
     // -- frame changes ---------------------------------------------------------
@@ -1942,7 +1952,7 @@ k_decode_acc(const DevCode *__restrict__ codes, FrameBatch fb, IterParams ip, St
         auto converged = [&](int buf) -> bool {  // identical result in every wave
             const float a = lane < W ? s_red[buf][0][lane] : 0.0f;
             const float b = lane < W ? s_red[buf][1][lane] : 0.0f;
-            return wave_sum(a) < thr && wave_sum(b) < thr;
+            return row0_sum(a) < thr && row0_sum(b) < thr;
         };
 
         int iters;
