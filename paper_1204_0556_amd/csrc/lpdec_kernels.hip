@@ -2205,7 +2205,7 @@ static hipError_t go_range(const LaunchConfig &cfg, const DevCode *codes, const 
             // degrees 6..8 are built for the resident form only
             if constexpr (!(DMIN == 6 && DMAX == 8)) {
                 // checks above degree 8 use the same builds: their per-check arrays spill
-                // 15-27 registers at the 128 a lane has here, but a build for 512 threads
+                // 11-18 registers at the 128 a lane has here, but a build for 512 threads
                 // (167 registers, no spills) ran the (3,13) n = 1057 code 1.37x slower in
                 // the persistent-global form at two workgroups per CU instead of three
                 switch (cfg.form) {
