@@ -2,8 +2,9 @@
 
 The package refuses to import without its library (there is no CPU fallback), so
 the build entry point must compile before anything imports the package.  This
-copies the sources (no shared objects, objects or scratch folders) to a temporary
-directory and runs build() there in a fresh interpreter."""
+copies the sources that build() needs (the package, the header, the oracle and the
+build entry point; no shared objects or objects) to a temporary directory and runs
+build() there in a fresh interpreter."""
 import os
 import shutil
 import subprocess
@@ -14,8 +15,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_build_from_a_tree_without_libraries(tmp_path):
     dst = tmp_path / "repo"
-    shutil.copytree(ROOT, dst, ignore=shutil.ignore_patterns(
-        "*.so", "*.o", ".git", "_work", "gpurun_out", "__pycache__", ".pytest_cache"))
+    dst.mkdir()
+    skip = shutil.ignore_patterns("*.so", "*.o", "__pycache__")
+    for d in ("paper_1204_0556_amd", "include", "oracle"):
+        shutil.copytree(os.path.join(ROOT, d), dst / d, ignore=skip)
+    shutil.copy2(os.path.join(ROOT, "__graft_entry__.py"), dst / "__graft_entry__.py")
     assert not (dst / "paper_1204_0556_amd" / "liblpdec.so").exists()
     r = subprocess.run([sys.executable, "-c", "import __graft_entry__ as g; g.build()"], cwd=dst,
                        capture_output=True, text=True, timeout=600)
